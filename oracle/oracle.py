@@ -1,0 +1,146 @@
+"""Python access to the CPU oracle (test infrastructure only).
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this module.  The product path never does.
+
+``build()`` compiles ``sse_oracle.c`` with gcc into ``liboracle.so`` next to
+this file; the functions below wrap its entry points for numpy complex128
+arrays.  See ``sse_oracle.c`` for the formula (Eq. 3 of the paper) and the
+layouts.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "sse_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+_lib = None
+
+
+def build(verbose: bool = False, src: str = SRC, out: str = LIB) -> str:
+    cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
+           "-fno-fast-math", "-ffp-contract=off", src, "-o", out + ".tmp", "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(out + ".tmp", out)
+    return out
+
+
+def _open(path):
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    lib.oracle_sse_points.argtypes = [P, P, P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_int64, P, P]
+    lib.oracle_sse_forward.argtypes = [P, P, P, P, P, ctypes.c_double, ctypes.c_double, P]
+    lib.oracle_sse_backward.argtypes = [P, P, P, P, P, ctypes.c_double, ctypes.c_double, P, P, P, P]
+    lib.oracle_num_threads.argtypes = []
+    for f in (lib.oracle_sse_points, lib.oracle_sse_forward, lib.oracle_sse_backward, lib.oracle_num_threads):
+        f.restype = ctypes.c_int
+    return lib
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        _lib = _open(LIB)
+    return _lib
+
+
+def _ptr(x):
+    return None if x is None else x.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dims_array(dims) -> np.ndarray:
+    return np.asarray(dims.as_tuple(), dtype=np.int64)
+
+
+def _check(arr, shape, dtype, name):
+    if arr.shape != tuple(shape) or arr.dtype != dtype or not arr.flags.c_contiguous:
+        raise ValueError(f"{name}: expected contiguous {dtype} {tuple(shape)}, got {arr.dtype} {arr.shape}")
+
+
+def _check_inputs(dims, G, D, dH, nbr):
+    _check(G, dims.g_shape, np.complex128, "G")
+    _check(D, dims.d_shape, np.complex128, "D")
+    _check(dH, dims.dh_shape, np.complex128, "dH")
+    _check(nbr, dims.nbr_shape, np.int32, "nbr")
+
+
+def num_threads(lib=None) -> int:
+    return int((lib or _load()).oracle_num_threads())
+
+
+def sse_forward(dims, G, D, dH, nbr, alpha=1j, lib=None) -> np.ndarray:
+    """Full Sigma[nkz, ne, na, norb, norb] (Eq. 3)."""
+    _check_inputs(dims, G, D, dH, nbr)
+    out = np.zeros(dims.sigma_shape, dtype=np.complex128)
+    dd = _dims_array(dims)
+    rc = (lib or _load()).oracle_sse_forward(_ptr(dd), _ptr(G), _ptr(D), _ptr(dH), _ptr(nbr),
+                                    float(np.real(alpha)), float(np.imag(alpha)), _ptr(out))
+    if rc:
+        raise RuntimeError(f"oracle_sse_forward failed with status {rc}")
+    return out
+
+
+def sse_points(dims, G, D, dH, nbr, pts, alpha=1j, lib=None) -> np.ndarray:
+    """Sigma blocks at output points pts[p] = (k, e, a); returns [npts, norb, norb]."""
+    _check_inputs(dims, G, D, dH, nbr)
+    pts = np.ascontiguousarray(np.asarray(pts, dtype=np.int64).reshape(-1, 3))
+    out = np.zeros((pts.shape[0], dims.norb, dims.norb), dtype=np.complex128)
+    dd = _dims_array(dims)
+    rc = (lib or _load()).oracle_sse_points(_ptr(dd), _ptr(G), _ptr(D), _ptr(dH), _ptr(nbr),
+                                   float(np.real(alpha)), float(np.imag(alpha)), pts.shape[0], _ptr(pts), _ptr(out))
+    if rc:
+        raise RuntimeError(f"oracle_sse_points failed with status {rc}")
+    return out
+
+
+def sse_backward(dims, G, D, dH, nbr, dSigma, alpha=1j, need=("G", "D", "dH"), lib=None):
+    """Gradients (dG, dD, ddH) of a real scalar with dL/dSigma = dSigma (PyTorch convention)."""
+    _check_inputs(dims, G, D, dH, nbr)
+    _check(dSigma, dims.sigma_shape, np.complex128, "dSigma")
+    dG = np.zeros(dims.g_shape, dtype=np.complex128) if "G" in need else None
+    dD = np.zeros(dims.d_shape, dtype=np.complex128) if "D" in need else None
+    ddH = np.zeros(dims.dh_shape, dtype=np.complex128) if "dH" in need else None
+    dd = _dims_array(dims)
+    rc = (lib or _load()).oracle_sse_backward(_ptr(dd), _ptr(G), _ptr(D), _ptr(dH), _ptr(nbr),
+                                     float(np.real(alpha)), float(np.imag(alpha)), _ptr(dSigma),
+                                     _ptr(dG), _ptr(dD), _ptr(ddH))
+    if rc:
+        raise RuntimeError(f"oracle_sse_backward failed with status {rc}")
+    return dG, dD, ddH
+
+
+def sse_status(dims_tuple, G, D, dH, nbr, lib=None) -> int:
+    """Raw status of the forward entry point for arbitrary (possibly invalid) dims."""
+    dd = np.asarray(dims_tuple, dtype=np.int64)
+    out = np.zeros(max(1, G.size), dtype=np.complex128)
+    return int((lib or _load()).oracle_sse_forward(_ptr(dd), _ptr(G), _ptr(D), _ptr(dH), _ptr(nbr), 0.0, 1.0, _ptr(out)))
+
+
+class Bound:
+    """The functions above bound to one loaded oracle library (used to run the
+    pins against deliberately broken copies of the oracle)."""
+
+    def __init__(self, path):
+        self.lib = _open(path)
+
+    def sse_forward(self, *a, **k):
+        return sse_forward(*a, lib=self.lib, **k)
+
+    def sse_points(self, *a, **k):
+        return sse_points(*a, lib=self.lib, **k)
+
+    def sse_backward(self, *a, **k):
+        return sse_backward(*a, lib=self.lib, **k)
+
+    def sse_status(self, *a, **k):
+        return sse_status(*a, lib=self.lib, **k)

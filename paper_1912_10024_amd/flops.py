@@ -1,0 +1,69 @@
+"""Flop and byte counts of the scattering self-energy contraction.
+
+Counting convention of the paper's computation model (Sec. "Performance
+Model", "Computation Model"): one complex Norb x Norb matrix product costs
+8*Norb^3 flops.
+"""
+from __future__ import annotations
+
+N3D = 3
+
+
+def f_eff(d) -> float:
+    """Effective (algorithmic) flops of one Sigma component (one of lesser/greater).
+
+    The regrouped form the paper arrives at after fission: one left product
+    X = grad_i H . G per (k', E', a, n, i) and one product X . Y per
+    (k, E, a, n, i, q, w, +/-):  8 Norb^3 * N3D * Nb * Na * Nkz * NE * (2 Nqz Nw + 1).
+    """
+    return 8.0 * d.norb ** 3 * N3D * d.nb * d.na * d.nkz * d.ne * (2 * d.nqz * d.nw + 1)
+
+
+def omen_sse_flops(na, nb, nkz, nqz, ne, nw, norb) -> float:
+    """The paper's count for the original OMEN SSE kernel (both components)."""
+    return 64.0 * na * nb * N3D * nkz * nqz * ne * nw * norb ** 3
+
+
+def dace_sse_flops(na, nb, nkz, nqz, ne, nw, norb, extra: int = 1) -> float:
+    """OMEN count reduced by 2 Nqz Nw / (Nqz Nw + extra).
+
+    The text states extra=1; the printed table is reproduced with extra=3.
+    """
+    return omen_sse_flops(na, nb, nkz, nqz, ne, nw, norb) * (nqz * nw + extra) / (2.0 * nqz * nw)
+
+
+def pd_gemm_flops(d) -> float:
+    """Real flops of the dense complex GEMM the HIP path runs on matrix cores.
+
+    Per atom, V[(k, w), (E', r, c)] = sum_{(k', n, i, j)} D_a[k - k', w, n, i, j] P[k', E', n, i, j, r, c]:
+    M = Nkz * Nw, K = Nkz * Nb * 9, N = NE * Norb^2, 8 flops per complex MAC.
+    """
+    return 8.0 * d.na * (d.nkz * d.nw) * (d.nkz * d.nb * 9) * (d.ne * d.norb ** 2)
+
+
+def pd_left_flops(d) -> float:
+    """Real flops of forming P = grad_i H . G . grad_j H^H (3 + 9 products per (k', E', a, n))."""
+    return 8.0 * d.norb ** 3 * 12 * d.nb * d.na * d.nkz * d.ne
+
+
+def pd_stencil_flops(d) -> float:
+    """Real adds of the (w, +/-) energy stencil: 2 complex adds per valid (k, E, w, s, r, c)."""
+    valid = 0
+    for e in range(d.ne):
+        for w in range(1, d.nw + 1):
+            valid += (0 <= e - w < d.ne) + (0 <= e + w < d.ne)
+    return 2.0 * d.na * d.nkz * valid * d.norb ** 2
+
+
+def pd_executed_flops(d) -> float:
+    return pd_gemm_flops(d) + pd_left_flops(d) + pd_stencil_flops(d)
+
+
+def min_bytes(d) -> float:
+    """Compulsory HBM traffic of one forward call: read G slot 0, D, grad H, nbr; write Sigma."""
+    blk = d.norb * d.norb * 16
+    g = d.nkz * d.ne * d.na * blk
+    sig = g
+    dd = d.nqz * d.nw * d.na * d.nb * 9 * 16
+    dh = d.na * d.nb * N3D * blk
+    return float(g + sig + dd + dh + d.na * d.nb * 4)

@@ -1,0 +1,69 @@
+"""The oracle's pins have teeth: plausible slips planted in a copy of the
+oracle (on the CPU) each make at least one pin fail.
+
+Every mutant is a one-line textual change of ``oracle/sse_oracle.c``
+(applied to its first occurrence, which is the forward loop nest), compiled
+with gcc into a temporary directory.  The mutated sources never leave the
+temporary directory.
+"""
+import os
+
+import pytest
+
+from oracle import oracle
+import test_oracle_pins as pins
+
+MUTANTS = {
+    "k_plus_q": ("((k - q) % d->nkz + d->nkz) % d->nkz", "((k + q) % d->nkz + d->nkz) % d->nkz"),
+    "one_energy_branch": ("for (int s = +1; s >= -1; s -= 2)", "for (int s = +1; s >= 1; s -= 2)"),
+    "freq_index": ("c_at(D, off_D(d, q, m - 1, a, n, i, j))", "c_at(D, off_D(d, q, m % d->nw, a, n, i, j))"),
+    "d_ij_swapped": ("c_at(D, off_D(d, q, m - 1, a, n, i, j))", "c_at(D, off_D(d, q, m - 1, a, n, j, i))"),
+    "transpose_not_adjoint": ("c_conj(c_at(Y, c * N + u))", "c_at(Y, c * N + u)"),
+    "adjoint_wrong_index": ("c_conj(c_at(Y, c * N + u))", "c_conj(c_at(Y, u * N + c))"),
+    "self_not_neighbour": ("const int64_t b = nbr[a * d->nb + n];", "const int64_t b = a;"),
+    "wrong_slot": ("* d->gs + 0)", "* d->gs + (d->gs > 1 ? 1 : 0))"),
+    "no_alpha": ("cplx v = c_mul(alpha, acc[x]);", "cplx v = acc[x];"),
+    "energy_edge": ("if (ep < 0 || ep >= d->ne) continue;", "if (ep < 1 || ep >= d->ne) continue;"),
+    "first_neighbour_only": ("for (int64_t n = 0; n < d->nb; ++n) {", "for (int64_t n = 0; n < 1; ++n) {"),
+    "right_product": ("mat_mul(N, A + 2 * off_A(d, a, n, i), Gb, T);", "mat_mul(N, Gb, A + 2 * off_A(d, a, n, i), T);"),
+    "two_directions": ("for (int i = 0; i < 3; ++i) {\n                        mat_mul", "for (int i = 0; i < 2; ++i) {\n                        mat_mul"),
+}
+
+
+def _pin_checks(lib):
+    """Run every forward pin against `lib`; return the names of the pins that fail."""
+    failed = []
+    checks = [
+        ("closed_form_a", lambda: pins.test_shifted_delta_closed_form_bit_exact(lib, 0, 1, 0, 0, 0)),
+        ("closed_form_b", lambda: pins.test_shifted_delta_closed_form_bit_exact(lib, 2, 3, 1, 1, 2)),
+        ("closed_form_c", lambda: pins.test_shifted_delta_closed_form_bit_exact(lib, 1, 5, 0, 0, 2)),
+        ("convolution_a", lambda: pins.test_single_ij_reduces_to_library_convolution(lib, 5, 1, 2, 2)),
+        ("convolution_b", lambda: pins.test_single_ij_reduces_to_library_convolution(lib, 1, 2, 1, 1)),
+        ("anti_hermitian", lambda: pins.test_anti_hermitian_output(lib, 1j, "anti")),
+        ("homogeneity", lambda: pins.test_homogeneity_and_linearity(lib)),
+        ("ne1_zero", lambda: pins.test_single_energy_point_is_zero(lib)),
+    ]
+    for name, fn in checks:
+        try:
+            fn()
+        except AssertionError:
+            failed.append(name)
+    return failed
+
+
+def test_unmutated_oracle_passes_all_pins():
+    assert _pin_checks(oracle.Bound(oracle.LIB if os.path.exists(oracle.LIB) else oracle.build())) == []
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(tmp_path, name):
+    old, new = MUTANTS[name]
+    src = open(oracle.SRC).read()
+    assert old in src, f"mutation site for {name} not found"
+    mutated = src.replace(old, new, 1)
+    path = tmp_path / f"mut_{name}.c"
+    path.write_text(mutated)
+    so = str(tmp_path / f"libmut_{name}.so")
+    oracle.build(src=str(path), out=so)
+    failed = _pin_checks(oracle.Bound(so))
+    assert failed, f"mutant {name} passed every pin"
