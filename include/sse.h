@@ -1,0 +1,160 @@
+/*
+ * sse.h -- C ABI of libsse, the MI355X (gfx950) implementation of the
+ * electron-phonon scattering self-energy of Ziogas et al., "A Data-Centric
+ * Approach to Extreme-Scale Ab initio Dissipative Quantum Transport
+ * Simulations" (SC'19).
+ *
+ * The operation (Eq. 3, Sec. "Current State of the Art"), for one of the
+ * lesser / greater components (the same superscript on G and D):
+ *
+ *   Sigma[k,E,a] = alpha * sum_{q=0}^{Nqz-1} sum_{w=1}^{Nw} sum_{s=+1,-1} [0 <= E - s*w < NE]
+ *                  * sum_{n=0}^{NB-1} sum_{i,j=0}^{2}
+ *                    D[q, w-1, a, n, i, j] * dH[a,n,i] . G[(k-q) mod Nkz, E - s*w, nbr[a,n], 0] . dH[a,n,j]^H
+ *
+ * - Only the diagonal Norb x Norb block of Sigma per atom is formed (the
+ *   paper keeps only the diagonal blocks of the electron SSE).
+ * - dH[a,n,i] = grad_i H for the pair (a, b = nbr[a,n]); grad_j H_ba is taken
+ *   as dH[a,n,j]^H (H is Hermitian).
+ * - D[q, w-1, a, n, :, :] is the phonon coefficient of the pair (a, nbr[a,n])
+ *   with the bracket (D_ba - D_bb - D_aa + D_ab) already formed; the phonon
+ *   frequency w*dE sits on the electron energy grid, w = 1..Nw.
+ * - Both energy branches E -/+ w use the same D; points outside the energy
+ *   grid contribute zero; the momentum grids coincide (Nqz = Nkz) and are
+ *   periodic, so kz - qz wraps around.
+ * - alpha carries the prefactor i of Eq. 3 and any quadrature weight of the
+ *   frequency integral the caller did not fold into D.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - All tensor pointers are HIP device pointers to row-major, contiguous
+ *   arrays.  "complex" means interleaved (re, im) doubles, i.e. the memory
+ *   of a complex128 tensor.  n3d is fixed at 3.
+ * - Shapes:
+ *     G       [nkz][ne][na][g_slots][norb][norb] complex; only slot 0 is read
+ *     D       [nqz][nw][na][nb][3][3]            complex
+ *     dH      [na][nb][3][norb][norb]            complex
+ *     nbr     [na][nb]                           int32, entries in [0, na)
+ *     Sigma   [nkz][ne][na][norb][norb]          complex (output)
+ *     dSigma  like Sigma; dG like G; dD like D; ddH like dH
+ * - Ownership: the caller allocates and frees every buffer, including the
+ *   workspace (size from sse_workspace_bytes).  The library keeps no device
+ *   allocations and does no host<->device copies, except sse_check_nbr.
+ * - Calls are asynchronous on `stream` (a hipStream_t; NULL = the default
+ *   stream).  Outputs are overwritten, never accumulated.  Inputs are only
+ *   read.  Calls that use distinct outputs and workspaces may run
+ *   concurrently.
+ * - Status codes (no exceptions cross this boundary; on any error no kernel
+ *   has been launched and no output has been touched):
+ *     SSE_OK 0, SSE_ERR_NULL 1 (required pointer is NULL), SSE_ERR_DIMS 2
+ *     (a dim <= 0, nqz != nkz, g_slots < 1, a size beyond the supported
+ *     limits, or an element count that overflows int64), SSE_ERR_WORKSPACE 3,
+ *     SSE_ERR_PRECISION 4, SSE_ERR_HIP 5 (the message carries
+ *     hipGetErrorString), SSE_ERR_NBR 6 (sse_check_nbr found an entry outside
+ *     [0, na)).
+ *   sse_last_error() returns a thread-local description of the last failure.
+ * - Kernels never read outside their inputs: a neighbour entry outside
+ *   [0, na) contributes zero (validate tables with sse_check_nbr).
+ */
+#ifndef SSE_H
+#define SSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SSE_ABI_VERSION 1
+
+typedef struct sse_dims {
+    int64_t nkz;     /* electron momentum points kz (periodic grid)              */
+    int64_t ne;      /* energy points                                            */
+    int64_t nqz;     /* phonon momentum points qz; must equal nkz                */
+    int64_t nw;      /* phonon frequencies w = 1..nw (units of the energy step)  */
+    int64_t na;      /* atoms                                                    */
+    int64_t nb;      /* neighbour slots per atom                                 */
+    int64_t norb;    /* orbitals per atom (block size)                           */
+    int64_t g_slots; /* size of G's block axis (slot 0 = diagonal block G_aa)    */
+} sse_dims;
+
+enum sse_precision {
+    SSE_FP64 = 0,    /* fp64 products on matrix cores, fp64 reduction           */
+    SSE_FP32 = 1,    /* products in fp32 (fp32 matrix cores), fp64 reduction    */
+    SSE_BF16X3 = 3   /* each fp32 operand split in three bf16 terms; the six
+                        products above 2^-24 on bf16 matrix cores with fp32
+                        accumulation; fp64 reduction                            */
+};
+
+enum sse_status {
+    SSE_OK = 0,
+    SSE_ERR_NULL = 1,
+    SSE_ERR_DIMS = 2,
+    SSE_ERR_WORKSPACE = 3,
+    SSE_ERR_PRECISION = 4,
+    SSE_ERR_HIP = 5,
+    SSE_ERR_NBR = 6
+};
+
+/* ABI version of the loaded library (SSE_ABI_VERSION of its build). */
+int sse_abi_version(void);
+
+/* Thread-local text of the last error (empty string if none). */
+const char* sse_last_error(void);
+
+/*
+ * Bytes of workspace a call needs.  backward = 0 for sse_forward with the
+ * given precision, 1 for sse_backward (precision ignored).  May be 0.
+ */
+int sse_workspace_bytes(const sse_dims* dims, int precision, int backward, size_t* bytes);
+
+/*
+ * Effective flops of one sse_forward call (one component), the paper's
+ * computation-model count for the regrouped form: one left product
+ * grad_i H . G per (kz', E', a, n, i) plus one product per
+ * (kz, E, a, n, i, qz, w, +/-), at 8 Norb^3 flops per complex product
+ * (Sec. "Computation Model"):
+ *   f_eff = 8 Norb^3 * 3 * NB * Na * Nkz * NE * (2 Nqz Nw + 1).
+ */
+int sse_effective_flops(const sse_dims* dims, double* f_eff);
+
+/*
+ * Sigma = the operation above (Eq. 3).  precision is an sse_precision value;
+ * every form reads the same fp64 inputs, gathers them in fp64 and reduces
+ * over (qz, w, +/-) in fp64.  Sigma is fully overwritten.
+ */
+int sse_forward(const sse_dims* dims, const double* G, const double* D, const double* dH,
+                const int32_t* nbr, double alpha_re, double alpha_im, int precision,
+                double* Sigma, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Adjoint of sse_forward (fp64) for a real scalar L, given dSigma = dL/dSigma
+ * in PyTorch's convention for complex gradients (dL/dRe z + i dL/dIm z).
+ * Writes dL/dG (slots >= 1 set to zero), dL/dD and dL/d(dH); any of the three
+ * output pointers may be NULL to skip that gradient.  Per valid term with
+ * d = D[q,w-1,a,n,i,j], A_i = dH[a,n,i], B = G[k',E',b,0], g = dSigma[k,E,a]:
+ *   dG[k',E',b,0]     += conj(alpha d) A_i^H g A_j
+ *   dD[q,w-1,a,n,i,j] += conj(alpha) sum_{r,c} conj((A_i B A_j^H)[r,c]) g[r,c]
+ *   ddH[a,n,i]        += conj(alpha d) g A_j B^H
+ *   ddH[a,n,j]        += alpha d g^H A_i B
+ * Shifted G blocks are re-gathered, not stored.
+ */
+int sse_backward(const sse_dims* dims, const double* G, const double* D, const double* dH,
+                 const int32_t* nbr, double alpha_re, double alpha_im, const double* dSigma,
+                 double* dG, double* dD, double* ddH, void* workspace, size_t workspace_bytes,
+                 void* stream);
+
+/*
+ * Synchronous check of a neighbour table: returns SSE_OK if every entry lies
+ * in [0, na), SSE_ERR_NBR otherwise.  Needs sse_workspace_bytes(dims, 0, 0)
+ * bytes of workspace, at least 4; copies one int32 back to the host and waits
+ * on `stream`.
+ */
+int sse_check_nbr(const sse_dims* dims, const int32_t* nbr, void* workspace, size_t workspace_bytes,
+                  void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSE_H */

@@ -1,0 +1,144 @@
+// C ABI of libsse: argument validation, workspace sizing and kernel dispatch.
+// Every check happens before any HIP call, so an invalid call launches nothing
+// and leaves every output untouched.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "sse_kernels.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int ok() {
+    g_err[0] = '\0';
+    return SSE_OK;
+}
+
+// a*b with overflow detection for non-negative operands
+bool mul_ok(int64_t a, int64_t b, int64_t* out) {
+    if (a < 0 || b < 0) return false;
+    if (a != 0 && b > INT64_MAX / a) return false;
+    *out = a * b;
+    return true;
+}
+
+bool count_ok(std::initializer_list<int64_t> xs) {
+    int64_t acc = 2;  // doubles per complex
+    for (int64_t x : xs)
+        if (!mul_ok(acc, x, &acc)) return false;
+    return true;
+}
+
+constexpr int64_t kMaxNorb = 32;
+
+int check_dims(const sse_dims* d) {
+    if (!d) return fail(SSE_ERR_NULL, "dims is NULL");
+    if (d->nkz <= 0 || d->ne <= 0 || d->nqz <= 0 || d->nw <= 0 || d->na <= 0 || d->nb <= 0 || d->norb <= 0 ||
+        d->g_slots <= 0)
+        return fail(SSE_ERR_DIMS, "every dim must be positive (nkz=%lld ne=%lld nqz=%lld nw=%lld na=%lld nb=%lld norb=%lld g_slots=%lld)",
+                    (long long)d->nkz, (long long)d->ne, (long long)d->nqz, (long long)d->nw, (long long)d->na,
+                    (long long)d->nb, (long long)d->norb, (long long)d->g_slots);
+    if (d->nqz != d->nkz) return fail(SSE_ERR_DIMS, "nqz (%lld) must equal nkz (%lld)", (long long)d->nqz, (long long)d->nkz);
+    if (d->norb > kMaxNorb) return fail(SSE_ERR_DIMS, "norb %lld exceeds the supported maximum %lld", (long long)d->norb, (long long)kMaxNorb);
+    if (d->na > INT32_MAX) return fail(SSE_ERR_DIMS, "na %lld does not fit the int32 neighbour table", (long long)d->na);
+    if (!count_ok({d->nkz, d->ne, d->na, d->g_slots, d->norb, d->norb}) || !count_ok({d->nqz, d->nw, d->na, d->nb, 9}) ||
+        !count_ok({d->na, d->nb, 3, d->norb, d->norb}) || !count_ok({d->nkz, d->ne, d->na, d->norb, d->norb}))
+        return fail(SSE_ERR_DIMS, "tensor sizes overflow int64");
+    return SSE_OK;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(SSE_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+}  // namespace
+
+extern "C" {
+
+int sse_abi_version(void) { return SSE_ABI_VERSION; }
+
+const char* sse_last_error(void) { return g_err; }
+
+int sse_workspace_bytes(const sse_dims* dims, int precision, int backward, size_t* bytes) {
+    int rc = check_dims(dims);
+    if (rc) return rc;
+    if (!bytes) return fail(SSE_ERR_NULL, "bytes is NULL");
+    if (!backward && precision != SSE_FP64 && precision != SSE_FP32 && precision != SSE_BF16X3)
+        return fail(SSE_ERR_PRECISION, "unknown precision %d", precision);
+    size_t ws = 256;  // status flag of sse_check_nbr
+    *bytes = ws;
+    return ok();
+}
+
+int sse_effective_flops(const sse_dims* dims, double* f_eff) {
+    int rc = check_dims(dims);
+    if (rc) return rc;
+    if (!f_eff) return fail(SSE_ERR_NULL, "f_eff is NULL");
+    const double n = (double)dims->norb;
+    *f_eff = 8.0 * n * n * n * 3.0 * (double)dims->nb * (double)dims->na * (double)dims->nkz * (double)dims->ne *
+             (2.0 * (double)dims->nqz * (double)dims->nw + 1.0);
+    return ok();
+}
+
+int sse_forward(const sse_dims* dims, const double* G, const double* D, const double* dH, const int32_t* nbr,
+                double alpha_re, double alpha_im, int precision, double* Sigma, void* workspace,
+                size_t workspace_bytes, void* stream) {
+    int rc = check_dims(dims);
+    if (rc) return rc;
+    if (!G || !D || !dH || !nbr || !Sigma) return fail(SSE_ERR_NULL, "a tensor pointer is NULL");
+    if (precision != SSE_FP64 && precision != SSE_FP32 && precision != SSE_BF16X3)
+        return fail(SSE_ERR_PRECISION, "unknown precision %d", precision);
+    size_t need = 0;
+    sse_workspace_bytes(dims, precision, 0, &need);
+    if (need > 0 && (workspace == nullptr || workspace_bytes < need))
+        return fail(SSE_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace_bytes);
+    const sse::Dims d = sse::to_dims(*dims);
+    const sse::cd alpha{alpha_re, alpha_im};
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (precision != SSE_FP64) return fail(SSE_ERR_PRECISION, "precision %d is not available for these dims", precision);
+    if (!sse::generic_supported(d)) return fail(SSE_ERR_DIMS, "no kernel for these dims");
+    hipError_t e = sse::launch_fwd_generic(d, G, D, dH, nbr, alpha, Sigma, s);
+    if (e != hipSuccess) return hip_fail(e, "forward launch");
+    return ok();
+}
+
+int sse_backward(const sse_dims* dims, const double* G, const double* D, const double* dH, const int32_t* nbr,
+                 double alpha_re, double alpha_im, const double* dSigma, double* dG, double* dD, double* ddH,
+                 void* workspace, size_t workspace_bytes, void* stream) {
+    int rc = check_dims(dims);
+    if (rc) return rc;
+    if (!G || !D || !dH || !nbr || !dSigma) return fail(SSE_ERR_NULL, "an input pointer is NULL");
+    (void)alpha_re; (void)alpha_im; (void)dG; (void)dD; (void)ddH; (void)workspace; (void)workspace_bytes; (void)stream;
+    return fail(SSE_ERR_DIMS, "backward not built yet");
+}
+
+int sse_check_nbr(const sse_dims* dims, const int32_t* nbr, void* workspace, size_t workspace_bytes, void* stream) {
+    int rc = check_dims(dims);
+    if (rc) return rc;
+    if (!nbr) return fail(SSE_ERR_NULL, "nbr is NULL");
+    if (!workspace || workspace_bytes < sizeof(int)) return fail(SSE_ERR_WORKSPACE, "workspace of at least 4 bytes needed");
+    const sse::Dims d = sse::to_dims(*dims);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int* flag = reinterpret_cast<int*>(workspace);
+    hipError_t e = sse::launch_check_nbr(d, nbr, flag, s);
+    if (e != hipSuccess) return hip_fail(e, "check_nbr launch");
+    int host_flag = 0;
+    e = hipMemcpyAsync(&host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "check_nbr copy");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "check_nbr sync");
+    if (host_flag) return fail(SSE_ERR_NBR, "neighbour table has an entry outside [0, %lld)", (long long)d.na);
+    return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,88 @@
+// Direct (term-by-term) forward kernel for shapes without a matrix-core
+// specialisation.  One workgroup per output block Sigma[k,E,a]; every term of
+// Eq. 3 is formed as (grad_i H . G_b) . grad_j H^H in fp64 on the vector ALUs.
+#include "sse_kernels.h"
+
+namespace sse {
+
+namespace {
+constexpr int kGenThreads = 256;
+constexpr int kGenMaxPerThread = 4;  // norb^2 <= 1024
+}  // namespace
+
+__global__ __launch_bounds__(kGenThreads) void fwd_generic_kernel(Dims d, const double* __restrict__ G,
+                                                                  const double* __restrict__ D,
+                                                                  const double* __restrict__ A,
+                                                                  const int32_t* __restrict__ nbr, cd alpha,
+                                                                  double* __restrict__ S) {
+    extern __shared__ double smem[];
+    const int N = (int)d.norb, NN = N * N;
+    cd* sG = reinterpret_cast<cd*>(smem);  // [N][N]
+    cd* sT = sG + NN;                      // [3][N][N]
+    const int tid = threadIdx.x;
+    const int64_t nblk = d.nkz * d.ne * d.na;
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const int64_t a = blk % d.na, e = (blk / d.na) % d.ne, k = blk / (d.na * d.ne);
+        cd acc[kGenMaxPerThread];
+#pragma unroll
+        for (int x = 0; x < kGenMaxPerThread; ++x) acc[x] = cd{0.0, 0.0};
+        for (int64_t q = 0; q < d.nqz; ++q) {
+            const int64_t kp = ((k - q) % d.nkz + d.nkz) % d.nkz;
+            for (int64_t w = 1; w <= d.nw; ++w) {
+                for (int s = 1; s >= -1; s -= 2) {
+                    const int64_t ep = e - s * w;
+                    if (ep < 0 || ep >= d.ne) continue;
+                    for (int64_t n = 0; n < d.nb; ++n) {
+                        const int64_t b = nbr[a * d.nb + n];
+                        if (b < 0 || b >= d.na) continue;
+                        const double* Gb = G + 2 * off_G(d, kp, ep, b);
+                        for (int x = tid; x < NN; x += kGenThreads) sG[x] = cload(Gb, x);
+                        __syncthreads();
+                        for (int x = tid; x < 3 * NN; x += kGenThreads) {
+                            const int i = x / NN, r = (x % NN) / N, u = x % N;
+                            const double* Ai = A + 2 * off_A(d, a, n, i);
+                            cd t = cd{0.0, 0.0};
+                            for (int tt = 0; tt < N; ++tt) cfma(t, cload(Ai, r * N + tt), sG[tt * N + u]);
+                            sT[x] = t;
+                        }
+                        __syncthreads();
+                        const double* Dq = D + 2 * off_D(d, q, w - 1, a, n);
+#pragma unroll
+                        for (int xi = 0; xi < kGenMaxPerThread; ++xi) {
+                            const int x = tid + xi * kGenThreads;
+                            if (x >= NN) break;
+                            const int r = x / N, c = x % N;
+                            for (int i = 0; i < 3; ++i)
+                                for (int j = 0; j < 3; ++j) {
+                                    const double* Aj = A + 2 * off_A(d, a, n, j);
+                                    cd u = cd{0.0, 0.0};
+                                    for (int uu = 0; uu < N; ++uu) cfma_conj(u, sT[i * NN + r * N + uu], cload(Aj, c * N + uu));
+                                    cfma(acc[xi], cload(Dq, i * 3 + j), u);
+                                }
+                        }
+                        __syncthreads();
+                    }
+                }
+            }
+        }
+        double* Sb = S + 2 * off_S(d, k, e, a);
+#pragma unroll
+        for (int xi = 0; xi < kGenMaxPerThread; ++xi) {
+            const int x = tid + xi * kGenThreads;
+            if (x < NN) cstore(Sb, x, cmul(alpha, acc[xi]));
+        }
+    }
+}
+
+hipError_t launch_fwd_generic(const Dims& d, const double* G, const double* D, const double* A, const int32_t* nbr,
+                              cd alpha, double* S, hipStream_t stream) {
+    const int64_t nblk = d.nkz * d.ne * d.na;
+    const unsigned grid = (unsigned)(nblk < (int64_t)(1 << 30) ? nblk : (1 << 30));
+    const size_t lds = sizeof(cd) * 4 * (size_t)(d.norb * d.norb);
+    hipLaunchKernelGGL(fwd_generic_kernel, dim3(grid), dim3(kGenThreads), lds, stream, d, G, D, A, nbr, alpha, S);
+    return hipGetLastError();
+}
+
+bool generic_supported(const Dims& d) { return d.norb * d.norb <= kGenThreads * kGenMaxPerThread; }
+
+}  // namespace sse

@@ -1,0 +1,16 @@
+// Launch entry points of the kernels behind the C ABI.
+#pragma once
+
+#include "sse_common.h"
+
+namespace sse {
+
+// direct term-by-term fp64 forward (any shape with norb^2 <= 1024)
+bool generic_supported(const Dims& d);
+hipError_t launch_fwd_generic(const Dims& d, const double* G, const double* D, const double* A, const int32_t* nbr,
+                              cd alpha, double* S, hipStream_t stream);
+
+// neighbour-table range check: sets *flag (device int) to 1 if any entry is outside [0, na)
+hipError_t launch_check_nbr(const Dims& d, const int32_t* nbr, int* flag, hipStream_t stream);
+
+}  // namespace sse

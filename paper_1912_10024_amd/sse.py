@@ -1,0 +1,154 @@
+"""PyTorch binding of libsse: argument marshalling only.
+
+Every step of the computation runs in the HIP kernels behind the C ABI
+(include/sse.h); PyTorch supplies device memory and the current stream.
+There is no fallback: if libsse.so is missing or the tensors are not on a HIP
+device, these functions raise.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from .inputs import Dims
+
+PRECISIONS = _lib.PRECISIONS
+
+
+def dims_of(G: torch.Tensor, D: torch.Tensor, dH: torch.Tensor, nbr: torch.Tensor) -> Dims:
+    if G.dim() != 6 or D.dim() != 6 or dH.dim() != 5 or nbr.dim() != 2:
+        raise ValueError("expected G[nkz,ne,na,slots,norb,norb], D[nqz,nw,na,nb,3,3], dH[na,nb,3,norb,norb], nbr[na,nb]")
+    nkz, ne, na, gs, norb, norb2 = G.shape
+    nqz, nw, na2, nb, three, three2 = D.shape
+    d = Dims(nkz=nkz, ne=ne, nqz=nqz, nw=nw, na=na, nb=nb, norb=norb, g_slots=gs)
+    if norb2 != norb or three != 3 or three2 != 3 or na2 != na:
+        raise ValueError(f"inconsistent shapes G{tuple(G.shape)} D{tuple(D.shape)}")
+    if tuple(dH.shape) != d.dh_shape:
+        raise ValueError(f"dH must be {d.dh_shape}, got {tuple(dH.shape)}")
+    if tuple(nbr.shape) != d.nbr_shape:
+        raise ValueError(f"nbr must be {d.nbr_shape}, got {tuple(nbr.shape)}")
+    return d
+
+
+def _check_tensor(t: torch.Tensor, name: str, dtype=torch.complex128):
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a HIP device, got {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _raise(rc: int, what: str):
+    if rc != _lib.SSE_OK:
+        raise RuntimeError(f"{what} failed (status {rc}): {_lib.last_error()}")
+
+
+def workspace(d: Dims, precision: str = "fp64", backward: bool = False, device="cuda") -> torch.Tensor:
+    lib = _lib.load()
+    nbytes = ctypes.c_size_t(0)
+    cd = _lib.SSEDims.of(d)
+    _raise(lib.sse_workspace_bytes(ctypes.byref(cd), PRECISIONS.get(precision, -1), int(backward), ctypes.byref(nbytes)),
+           "sse_workspace_bytes")
+    return torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device=device)
+
+
+def effective_flops(d: Dims) -> float:
+    lib = _lib.load()
+    out = ctypes.c_double(0.0)
+    cd = _lib.SSEDims.of(d)
+    _raise(lib.sse_effective_flops(ctypes.byref(cd), ctypes.byref(out)), "sse_effective_flops")
+    return float(out.value)
+
+
+def check_nbr(nbr: torch.Tensor, na: int) -> None:
+    """Raise if any neighbour entry lies outside [0, na) (synchronous)."""
+    _check_tensor(nbr, "nbr", torch.int32)
+    lib = _lib.load()
+    d = Dims(nkz=1, ne=1, nqz=1, nw=1, na=na, nb=nbr.shape[1], norb=1, g_slots=1)
+    ws = workspace(d, device=nbr.device)
+    cd = _lib.SSEDims.of(d)
+    _raise(lib.sse_check_nbr(ctypes.byref(cd), _ptr(nbr), _ptr(ws), ws.numel(), _stream(nbr.device)), "sse_check_nbr")
+
+
+def forward(G, D, dH, nbr, alpha=1j, precision: str = "fp64", out=None, ws=None) -> torch.Tensor:
+    """Sigma[nkz, ne, na, norb, norb] = Eq. 3 (one of lesser/greater)."""
+    d = dims_of(G, D, dH, nbr)
+    for t, n in ((G, "G"), (D, "D"), (dH, "dH")):
+        _check_tensor(t, n)
+    _check_tensor(nbr, "nbr", torch.int32)
+    if precision not in PRECISIONS:
+        raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+    if out is None:
+        out = torch.empty(d.sigma_shape, dtype=torch.complex128, device=G.device)
+    else:
+        _check_tensor(out, "out")
+        if tuple(out.shape) != d.sigma_shape:
+            raise ValueError(f"out must be {d.sigma_shape}")
+    if ws is None:
+        ws = workspace(d, precision, device=G.device)
+    lib = _lib.load()
+    cd = _lib.SSEDims.of(d)
+    a = complex(alpha)
+    rc = lib.sse_forward(ctypes.byref(cd), _ptr(G), _ptr(D), _ptr(dH), _ptr(nbr), a.real, a.imag,
+                         PRECISIONS[precision], _ptr(out), _ptr(ws), ws.numel(), _stream(G.device))
+    _raise(rc, "sse_forward")
+    return out
+
+
+def backward(G, D, dH, nbr, dSigma, alpha=1j, need=(True, True, True), ws=None):
+    """(dL/dG, dL/dD, dL/d dH) for dSigma = dL/dSigma (PyTorch complex-gradient convention)."""
+    d = dims_of(G, D, dH, nbr)
+    for t, n in ((G, "G"), (D, "D"), (dH, "dH"), (dSigma, "dSigma")):
+        _check_tensor(t, n)
+    _check_tensor(nbr, "nbr", torch.int32)
+    if tuple(dSigma.shape) != d.sigma_shape:
+        raise ValueError(f"dSigma must be {d.sigma_shape}")
+    dev = G.device
+    dG = torch.empty(d.g_shape, dtype=torch.complex128, device=dev) if need[0] else None
+    dD = torch.empty(d.d_shape, dtype=torch.complex128, device=dev) if need[1] else None
+    ddH = torch.empty(d.dh_shape, dtype=torch.complex128, device=dev) if need[2] else None
+    if ws is None:
+        ws = workspace(d, backward=True, device=dev)
+    lib = _lib.load()
+    cd = _lib.SSEDims.of(d)
+    a = complex(alpha)
+    rc = lib.sse_backward(ctypes.byref(cd), _ptr(G), _ptr(D), _ptr(dH), _ptr(nbr), a.real, a.imag, _ptr(dSigma),
+                          _ptr(dG), _ptr(dD), _ptr(ddH), _ptr(ws), ws.numel(), _stream(dev))
+    _raise(rc, "sse_backward")
+    return dG, dD, ddH
+
+
+class SSEFunction(torch.autograd.Function):
+    """Sigma = SSE(G, D, dH) with the hand-written adjoint as backward.
+
+    Saves only the inputs; the backward re-gathers the shifted G blocks.
+    """
+
+    @staticmethod
+    def forward(ctx, G, D, dH, nbr, alpha=1j):
+        ctx.save_for_backward(G, D, dH, nbr)
+        ctx.alpha = complex(alpha)
+        return forward(G, D, dH, nbr, alpha=alpha)
+
+    @staticmethod
+    def backward(ctx, gS):
+        G, D, dH, nbr = ctx.saved_tensors
+        need = ctx.needs_input_grad[:3]
+        dG, dD, ddH = backward(G, D, dH, nbr, gS.contiguous(), alpha=ctx.alpha, need=need)
+        return dG, dD, ddH, None, None
+
+
+def sse(G, D, dH, nbr, alpha=1j):
+    """Differentiable Sigma (autograd through the hand-written adjoint)."""
+    return SSEFunction.apply(G, D, dH, nbr, alpha)

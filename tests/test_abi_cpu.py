@@ -1,0 +1,99 @@
+"""The C-ABI library loads, exports every declared symbol and rejects bad
+calls before touching the GPU (runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1912_10024_amd import _lib, flops
+from paper_1912_10024_amd.inputs import CONFIGS, Dims
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(sse_\w+)\s*\(", txt))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    declared = _declared()
+    assert {"sse_forward", "sse_backward", "sse_workspace_bytes", "sse_check_nbr", "sse_effective_flops",
+            "sse_last_error", "sse_abi_version"} <= declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(_lib.EXPORTS) <= declared
+
+
+def test_abi_version(lib):
+    txt = open(os.path.join(ROOT, "include", "sse.h")).read()
+    v = int(re.search(r"#define SSE_ABI_VERSION (\d+)", txt).group(1))
+    assert lib.sse_abi_version() == v
+
+
+def _call_forward(lib, d, ptrs=(1, 1, 1, 1), out=1, precision=0, ws=None, wsb=0):
+    cd = _lib.SSEDims(*d) if isinstance(d, tuple) else _lib.SSEDims.of(d)
+    P = ctypes.c_void_p
+    G, D, dH, nbr = (P(x) if x else None for x in ptrs)
+    return lib.sse_forward(ctypes.byref(cd), G, D, dH, nbr, 0.0, 1.0, precision, P(out) if out else None,
+                           P(ws) if ws else None, wsb, None)
+
+
+@pytest.mark.parametrize("bad", [
+    (0, 4, 0, 2, 3, 2, 2, 1), (3, -1, 3, 2, 3, 2, 2, 1), (3, 4, 2, 2, 3, 2, 2, 1),  # nqz != nkz
+    (3, 4, 3, 2, 3, 2, 2, 0), (3, 4, 3, 2, 3, 2, 33, 1), (1 << 40, 1 << 40, 1 << 40, 2, 3, 2, 2, 1)])
+def test_bad_dims_rejected_before_launch(lib, bad):
+    assert _call_forward(lib, bad) == _lib.SSE_ERR_DIMS
+    assert lib.sse_last_error()
+
+
+def test_null_pointers_rejected(lib):
+    d = CONFIGS["tiny"]
+    for i in range(4):
+        ptrs = [1, 1, 1, 1]
+        ptrs[i] = 0
+        assert _call_forward(lib, d, ptrs=tuple(ptrs)) == _lib.SSE_ERR_NULL
+    assert _call_forward(lib, d, out=0) == _lib.SSE_ERR_NULL
+    assert lib.sse_forward(None, None, None, None, None, 0.0, 0.0, 0, None, None, 0, None) == _lib.SSE_ERR_NULL
+
+
+def test_bad_precision_rejected(lib):
+    assert _call_forward(lib, CONFIGS["tiny"], precision=7) == _lib.SSE_ERR_PRECISION
+    assert "precision" in lib.sse_last_error().decode()
+
+
+def test_workspace_too_small_rejected(lib):
+    d = CONFIGS["mid"]
+    need = ctypes.c_size_t(0)
+    cd = _lib.SSEDims.of(d)
+    assert lib.sse_workspace_bytes(ctypes.byref(cd), 0, 0, ctypes.byref(need)) == 0
+    if need.value > 0:
+        assert _call_forward(lib, d, ws=None, wsb=0) == _lib.SSE_ERR_WORKSPACE
+
+
+def test_effective_flops_matches_model(lib):
+    for d in CONFIGS.values():
+        out = ctypes.c_double(0)
+        cd = _lib.SSEDims.of(d)
+        assert lib.sse_effective_flops(ctypes.byref(cd), ctypes.byref(out)) == 0
+        assert out.value == flops.f_eff(d)
+
+
+def test_backward_and_check_reject_bad_input(lib):
+    cd = _lib.SSEDims(3, 4, 2, 2, 3, 2, 2, 1)
+    assert lib.sse_backward(ctypes.byref(cd), *([ctypes.c_void_p(1)] * 4), 0.0, 1.0, ctypes.c_void_p(1),
+                            None, None, None, None, 0, None) == _lib.SSE_ERR_DIMS
+    good = _lib.SSEDims.of(CONFIGS["tiny"])
+    assert lib.sse_check_nbr(ctypes.byref(good), None, ctypes.c_void_p(1), 256, None) == _lib.SSE_ERR_NULL
+    assert lib.sse_check_nbr(ctypes.byref(good), ctypes.c_void_p(1), None, 0, None) == _lib.SSE_ERR_WORKSPACE
