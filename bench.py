@@ -1,0 +1,181 @@
+"""Benchmark of the scattering self-energy forward on one MI355X.
+
+Workload: the device-scale electron-phonon problem (one GPU's share of a
+~5k-atom FinFET slice): Nkz=Nqz=7, NE=1024, Nw=10, Na=4864, Nb=4, Norb=10,
+complex128, G stored diagonal-only.  Inputs are seeded synthetic data drawn
+on the GPU (see paper_1912_10024_amd/inputs.py); they are resident in HBM
+before the timed region.  One step = one sse_forward call (one of
+Sigma^< / Sigma^>), i.e. every stage of the hot path over the whole input.
+
+Prints one JSON line (rank 0).  `value` is effective TFLOP/s, the paper's
+regrouped-form flop count (f_eff) divided by the time per step.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP64_MFMA_PEAK = 78.6e12   # MI355X dense fp64 matrix peak, flop/s
+FP32_MFMA_PEAK = 157.3e12
+BF16_MFMA_PEAK = 2.5e15
+HBM_PEAK = 8.0e12
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--config", default="device", choices=["tiny", "mid", "device"])
+    p.add_argument("--precision", default="fp64")
+    p.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle baseline sample")
+    p.add_argument("--no-cpu", action="store_true")
+    return p.parse_args()
+
+
+def compact_problem(d, G, D, dH, nbr, atoms):
+    """Host copy of everything the outputs of `atoms` depend on, with atoms renumbered."""
+    import torch
+    from paper_1912_10024_amd.inputs import Dims
+
+    nbr_h = nbr.cpu().numpy()
+    keep = sorted(set(int(a) for a in atoms) | set(int(b) for a in atoms for b in nbr_h[a]))
+    remap = {a: i for i, a in enumerate(keep)}
+    idx = torch.tensor(keep, device=G.device)
+    sub = Dims(nkz=d.nkz, ne=d.ne, nqz=d.nqz, nw=d.nw, na=len(keep), nb=d.nb, norb=d.norb, g_slots=1)
+    Gs = G[:, :, :, :1].index_select(2, idx).cpu().numpy()
+    Ds = D.index_select(2, idx).cpu().numpy()
+    Hs = dH.index_select(0, idx).cpu().numpy()
+    # atoms outside `atoms` keep a valid (unused) neighbour row: point at themselves' first kept atom
+    nb_s = np.zeros((len(keep), d.nb), dtype=np.int32)
+    for a in keep:
+        if a in set(int(x) for x in atoms):
+            nb_s[remap[a]] = [remap[int(b)] for b in nbr_h[a]]
+        else:
+            nb_s[remap[a]] = [(remap[a] + 1 + t) % len(keep) for t in range(d.nb)]
+    return sub, np.ascontiguousarray(Gs), np.ascontiguousarray(Ds), np.ascontiguousarray(Hs), nb_s, remap
+
+
+def cpu_baseline(d, G, D, dH, nbr, S, target_s, f_block, seed=7):
+    """Time the CPU oracle on a bounded sample of output blocks of this workload
+    and check those blocks against the GPU result."""
+    from oracle import oracle
+
+    rng = np.random.default_rng(seed)
+    atoms = rng.choice(d.na, size=4, replace=False)
+    sub, Gs, Ds, Hs, nbs, remap = compact_problem(d, G, D, dH, nbr, atoms)
+    oracle.num_threads()
+
+    def pts_for(n):
+        ks = rng.integers(d.nkz, size=n)
+        es = rng.integers(d.ne, size=n)
+        aa = rng.choice(atoms, size=n)
+        return [(int(k), int(e), int(a)) for k, e, a in zip(ks, es, aa)]
+
+    # calibrate, then run a sample sized to target_s
+    cal = pts_for(8)
+    t0 = time.perf_counter()
+    oracle.sse_points(sub, Gs, Ds, Hs, nbs, [(k, e, remap[a]) for k, e, a in cal])
+    per = (time.perf_counter() - t0) / len(cal)
+    n = int(max(8, min(4096, target_s / max(per, 1e-6))))
+    pts = pts_for(n)
+    t0 = time.perf_counter()
+    ref = oracle.sse_points(sub, Gs, Ds, Hs, nbs, [(k, e, remap[a]) for k, e, a in pts])
+    t = time.perf_counter() - t0
+    got = np.stack([S[k, e, a].cpu().numpy() for k, e, a in pts])
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    return {
+        "value": n * f_block / t / 1e12,
+        "unit": "TFLOP/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"{n} output blocks Sigma[kz,E,a] (4 seeded atoms, random kz,E) of the same workload, {t:.1f} s",
+        "seconds": t,
+        "gpu_vs_oracle_rel_err": err,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    from paper_1912_10024_amd import flops, sse
+    from paper_1912_10024_amd.inputs import CONFIGS, CONFIG_INDEX, generate_device
+
+    d = CONFIGS[args.config]
+    dev = torch.device("cuda:0")
+    t_gen = time.perf_counter()
+    inp = generate_device(d, CONFIG_INDEX[args.config], device=dev)
+    G, D, dH, nbr = inp["G<"], inp["D<"], inp["dH"], inp["nbr"]
+    sse.check_nbr(nbr, d.na)
+    S = torch.empty(d.sigma_shape, dtype=torch.complex128, device=dev)
+    ws = sse.workspace(d, args.precision, device=dev)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+
+    for _ in range(args.warmup):
+        sse.forward(G, D, dH, nbr, precision=args.precision, out=S, ws=ws)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        ev[s][0].record(stream)
+        sse.forward(G, D, dH, nbr, precision=args.precision, out=S, ws=ws)
+        ev[s][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = [a.elapsed_time(b) for a, b in ev]
+    ms = float(np.mean(kern_ms))
+    f_eff = flops.f_eff(d)
+    gemm = flops.pd_gemm_flops(d)
+    value = f_eff / (ms * 1e-3) / 1e12
+    peak = {"fp64": FP64_MFMA_PEAK, "fp32": FP32_MFMA_PEAK, "bf16x3": BF16_MFMA_PEAK}[args.precision]
+    achieved = gemm / (ms * 1e-3)
+    line = {
+        "metric": "SSE effective TFLOP/s (fp64, one Sigma component)",
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else args.precision,
+        "data": "synthetic",
+        "config": {"workload": f"electron-phonon SSE Sigma^< forward, {args.config}",
+                   "nkz": d.nkz, "ne": d.ne, "nqz": d.nqz, "nw": d.nw, "na": d.na, "nb": d.nb,
+                   "norb": d.norb, "g_slots": d.g_slots, "precision": args.precision},
+        "kernel_ms": round(ms, 3),
+        "kernel_ms_all": [round(x, 3) for x in kern_ms],
+        "f_eff": f_eff,
+        "roofline": {"bound": "mfma", "achieved": round(achieved / 1e12, 3), "peak": peak / 1e12,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "flops_per_launch": gemm, "what": "dense P.D GEMM flops on matrix cores"},
+        "executed_flops_per_launch": flops.pd_executed_flops(d),
+        "input_gen_s": round(t_gen, 2),
+    }
+    if not args.no_cpu:
+        f_block = f_eff / (d.nkz * d.ne * d.na)
+        line["cpu_baseline"] = cpu_baseline(d, G, D, dH, nbr, S, args.cpu_seconds, f_block)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -106,8 +106,13 @@ int sse_forward(const sse_dims* dims, const double* G, const double* D, const do
     const sse::cd alpha{alpha_re, alpha_im};
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (precision != SSE_FP64) return fail(SSE_ERR_PRECISION, "precision %d is not available for these dims", precision);
-    if (!sse::generic_supported(d)) return fail(SSE_ERR_DIMS, "no kernel for these dims");
-    hipError_t e = sse::launch_fwd_generic(d, G, D, dH, nbr, alpha, Sigma, s);
+    hipError_t e;
+    if (sse::fwd64_specialised(d)) {
+        e = sse::launch_fwd_mfma64(d, G, D, dH, nbr, alpha, Sigma, s);
+    } else {
+        if (!sse::generic_supported(d)) return fail(SSE_ERR_DIMS, "no kernel for these dims");
+        e = sse::launch_fwd_generic(d, G, D, dH, nbr, alpha, Sigma, s);
+    }
     if (e != hipSuccess) return hip_fail(e, "forward launch");
     return ok();
 }
