@@ -105,11 +105,12 @@ int sse_forward(const sse_dims* dims, const double* G, const double* D, const do
     const sse::Dims d = sse::to_dims(*dims);
     const sse::cd alpha{alpha_re, alpha_im};
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    if (precision != SSE_FP64) return fail(SSE_ERR_PRECISION, "precision %d is not available for these dims", precision);
     hipError_t e;
-    if (sse::fwd64_specialised(d)) {
-        e = sse::launch_fwd_mfma64(d, G, D, dH, nbr, alpha, Sigma, s);
+    if (sse::fwd_mfma_specialised(d) && (precision == SSE_FP64 || precision == SSE_FP32)) {
+        e = sse::launch_fwd_mfma(d, precision, G, D, dH, nbr, alpha, Sigma, s);
     } else {
+        if (precision != SSE_FP64)
+            return fail(SSE_ERR_PRECISION, "precision %d has no kernel for these dims", precision);
         if (!sse::generic_supported(d)) return fail(SSE_ERR_DIMS, "no kernel for these dims");
         e = sse::launch_fwd_generic(d, G, D, dH, nbr, alpha, Sigma, s);
     }

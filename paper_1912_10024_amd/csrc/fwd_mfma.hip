@@ -1,0 +1,427 @@
+// FP64 matrix-core forward kernel of the scattering self-energy (Eq. 3).
+//
+// Regrouping (the fission of Sec. "Dataflow Optimizations", taken one step
+// further so the matrix cores see one dense GEMM per atom):
+//
+//   P[k',E',n,i,j] = grad_i H_{a,n} . G[k',E',nbr[a,n],0] . grad_j H_{a,n}^H     (Norb x Norb)
+//   V[(k,w),(E',r,c)] = sum_{k',n,i,j} D[(k-k') mod Nkz, w-1, a, n, i, j] * P[k',E',n,i,j][r,c]
+//   Sigma[k,E,a][r,c] = alpha * sum_w ( V[(k,w),(E-w,r,c)] + V[(k,w),(E+w,r,c)] )
+//
+// The momentum convolution (sum over qz with k' = k - qz) sits inside the
+// GEMM's K dimension: the D operand is the circulant block matrix
+// D[(k - k') mod Nkz], built on the fly from a per-atom table in LDS.  The
+// energy convolution (w, +/-) is the stencil applied to the GEMM output.
+//
+// Work decomposition: one workgroup of 8 waves per (atom a, output row r);
+// it sweeps the energy axis in blocks of EB source energies.  Per block the
+// GEMM is M = 2*Nkz*Nw real rows (k, w, re/im), N = EB*Norb columns (E', c),
+// K = Nkz * Nb * 9 complex, consumed in chunks of one k' and two neighbours
+// (36 real K rows = 9 MFMA k-steps).  Complex products use the real
+// embedding [[Dr, -Di], [Di, Dr]] . [Pr; Pi].
+//
+// Pipeline per chunk (one barrier): every wave issues its share of the
+// 16x16x4 fp64 MFMAs on the P chunk in LDS, forms the next P chunk from the
+// X = grad_i H . G rows of the chunk after (vector ALUs, double-buffered
+// in LDS), and gathers the G blocks for the chunk after that from HBM.  The
+// waves on one SIMD alternate which of the two they do first, so one wave's
+// vector work runs under the other's matrix instructions.  At the end of an
+// energy block each wave adds its accumulators into a ring of output planes
+// (LDS, fp64), in wave order so that results are bitwise reproducible;
+// planes that can receive no more contributions are scaled by alpha and
+// written out.
+#include "sse_kernels.h"
+
+namespace sse {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Operand type of the matrix-core GEMM: fp64 (16x16x4 f64 MFMA) or fp32
+// (16x16x4 f32 MFMA, fp32 accumulation over one K chunk, then fp64).
+template <int PREC>
+struct Oper;
+template <>
+struct Oper<SSE_FP64> {
+    using T = double;
+    using Acc = f64x4;
+    static __device__ __forceinline__ Acc mma(T a, T b, Acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    static __device__ __forceinline__ T neg_if(T x, bool neg) {
+        return __longlong_as_double(__double_as_longlong(x) ^ (neg ? (long long)0x8000000000000000ull : 0ll));
+    }
+    // C[i][j] of a 16x16 tile sits in lane j + 16*(i%4), register i/4
+    static __device__ __forceinline__ int row_of(int lane, int v) { return 4 * v + (lane >> 4); }
+};
+template <>
+struct Oper<SSE_FP32> {
+    using T = float;
+    using Acc = f32x4;
+    static __device__ __forceinline__ Acc mma(T a, T b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    static __device__ __forceinline__ T neg_if(T x, bool neg) {
+        return __int_as_float(__float_as_int(x) ^ (neg ? (int)0x80000000u : 0));
+    }
+    // C[i][j] of a 16x16 tile sits in lane j + 16*(i/4), register i%4
+    static __device__ __forceinline__ int row_of(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+template <int NORB, int NKZ, int NW, int NB, int EB, int PREC>
+struct Fwd64 {
+    using T = typename Oper<PREC>::T;
+    static constexpr int WAVES = 8, THREADS = 64 * WAVES;
+    static constexpr int MROWS = 2 * NKZ * NW;
+    static constexpr int MT = (MROWS + 15) / 16;
+    static constexpr int NCOLS = EB * NORB;
+    static constexpr int NT = (NCOLS + 15) / 16;
+    static constexpr int NCP = NT * 16;
+    static constexpr int NP = (NB + 1) / 2;      // neighbour pairs per k'
+    static constexpr int NB2 = 2 * NP;           // neighbour slots in the D table (odd NB padded)
+    static constexpr int NCHUNK = NKZ * NP;
+    static constexpr int KR = 36;
+    static constexpr int KS = 9;
+    static constexpr int RING = EB + 2 * NW;
+    static constexpr int WS = NB2 * 18 + 2;      // D-table stride per w, padded to spread LDS banks
+    static constexpr int QS = NW * WS;
+    static constexpr int ZOFF = NKZ * QS;        // zero region read by padding rows
+    static constexpr int NN = NORB * NORB;
+    // wave -> M-tile ownership: waves own whole M-tiles (all N-tiles); the
+    // M-tiles past the eighth are dealt out one (M-tile, N-tile) pair per wave
+    static constexpr int OWN = MT < WAVES ? MT : WAVES;
+    static constexpr int XP = MT > WAVES ? (MT - WAVES) * NT : 0;
+    // LDS carve-up: D table and P chunks in the operand type, the rest in doubles
+    static constexpr int L_D = ZOFF + NP * 36 + 4;
+    static constexpr int L_A = NB * 3 * NN * 2;
+    static constexpr int L_P = 2 * KR * NCP;
+    static constexpr int XB = EB * 2 * 3 * NORB * 2;  // one X buffer: [el][nl][i][u] complex
+    static constexpr int L_X = 2 * XB;
+    static constexpr int RP = NKZ * NORB * 2;  // one ring plane: [k][c] complex
+    static constexpr int L_R = RING * RP;
+    static constexpr int OPER_DOUBLES = ((L_D + L_P) * (int)sizeof(T) + 7) / 8;
+    static constexpr size_t LDS_BYTES = sizeof(double) * (size_t)(OPER_DOUBLES + L_A + L_X + L_R);
+    static constexpr int X_ITEMS = EB * 2 * 3 * NORB;  // (el, nl, i, u)
+    static constexpr int X_IPW = (X_ITEMS + WAVES - 1) / WAVES;
+    static constexpr int P_ITEMS = EB * 2 * NORB * 3;  // (el, nl, c, i)
+    static constexpr int P_IPW = (P_ITEMS + WAVES - 1) / WAVES;
+    static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
+    static_assert(X_IPW <= 64 && P_IPW <= 64, "one item per lane");
+    static_assert(XP <= WAVES, "at most one extra (M-tile, N-tile) pair per wave");
+};
+
+template <int NORB, int NKZ, int NW, int NB, int EB, int PREC>
+__global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __restrict__ G,
+                                                       const double* __restrict__ Dg,
+                                                       const double* __restrict__ Ag,
+                                                       const int32_t* __restrict__ nbr, cd alpha,
+                                                       double* __restrict__ S) {
+    using C = Fwd64<NORB, NKZ, NW, NB, EB, PREC>;
+    using O = Oper<PREC>;
+    using T = typename O::T;
+    extern __shared__ double lds[];
+    T* sD = reinterpret_cast<T*>(lds);
+    T* sP = sD + C::L_D;
+    double* sA = lds + C::OPER_DOUBLES;
+    double* sX = sA + C::L_A;
+    double* sR = sX + C::L_X;
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    // XCD-aware mapping: the Norb workgroups of one atom share its D, grad H and
+    // neighbour G blocks, so they get block ids that land on the same XCD.
+    const int64_t bid = blockIdx.x;
+    const int r = (int)((bid >> 3) % NORB);
+    const int64_t a = ((bid >> 3) / NORB) * 8 + (bid & 7);
+    if (a >= d.na) return;  // uniform for the whole workgroup, before any barrier
+
+    // ---- stage the atom's D table, grad H; clear buffers
+    for (int x = tid; x < C::L_D; x += C::THREADS) sD[x] = T(0);
+    __syncthreads();
+    for (int x = tid; x < NKZ * NW * NB * 9; x += C::THREADS) {
+        const int ij = x % 9, n = (x / 9) % NB, w = (x / (9 * NB)) % NW, q = x / (9 * NB * NW);
+        const cd v = cload(Dg, off_D(d, q, w, a, n) + ij);
+        sD[q * C::QS + w * C::WS + n * 18 + ij * 2] = T(v.re);
+        sD[q * C::QS + w * C::WS + n * 18 + ij * 2 + 1] = T(v.im);
+    }
+    for (int x = tid; x < NB * 3 * C::NN; x += C::THREADS) {
+        const cd v = cload(Ag, off_A(d, a, 0, 0) + x);
+        sA[2 * x] = v.re;
+        sA[2 * x + 1] = v.im;
+    }
+    for (int x = tid; x < C::L_P; x += C::THREADS) sP[x] = T(0);
+    for (int x = tid; x < C::L_R; x += C::THREADS) sR[x] = 0.0;
+
+    const int64_t NE = d.ne;
+    const int64_t nblk = (NE + EB - 1) / EB;
+    const int64_t niter = nblk * C::NCHUNK;
+    const int kk = lane >> 4, kap = kk & 1, j16 = lane & 15;
+
+    // ---- X rows, step 1: gather this lane's G column for chunk g into registers
+    const int x_item = wave * C::X_IPW + lane;
+    const bool x_lane = lane < C::X_IPW && x_item < C::X_ITEMS;
+    const int x_u = x_item % NORB, x_i = (x_item / NORB) % 3, x_nl = (x_item / (3 * NORB)) % 2,
+              x_el = x_item / (6 * NORB);
+    cd gv[NORB];
+    auto gather_g = [&](int64_t g) {
+#pragma unroll
+        for (int t = 0; t < NORB; ++t) gv[t] = cd{0.0, 0.0};
+        if (g >= niter || !x_lane) return;
+        const int64_t blk = g / C::NCHUNK;
+        const int ch = (int)(g % C::NCHUNK), kp = ch / C::NP, np = ch % C::NP;
+        const int n = 2 * np + x_nl;
+        const int64_t e = blk * EB + x_el;
+        if (n >= NB || e >= NE) return;
+        const int32_t b = nbr[a * NB + n];
+        if (b < 0 || b >= d.na) return;  // out-of-range neighbour contributes zero
+        const double* Gb = G + 2 * off_G(d, kp, e, b);
+#pragma unroll
+        for (int t = 0; t < NORB; ++t) gv[t] = cload(Gb, t * NORB + x_u);
+    };
+    // ---- X rows, step 2: X[el][nl][i][u] = sum_t gradH[n][i][r][t] G[t][u]
+    auto finish_x = [&](int64_t g) {
+        if (g >= niter || !x_lane) return;
+        const int ch = (int)(g % C::NCHUNK), np = ch % C::NP;
+        const int n = 2 * np + x_nl;
+        cd acc{0.0, 0.0};
+        if (n < NB) {
+            const double* Ar = sA + 2 * ((n * 3 + x_i) * C::NN + r * NORB);
+#pragma unroll
+            for (int t = 0; t < NORB; ++t) cfma(acc, cd{Ar[2 * t], Ar[2 * t + 1]}, gv[t]);
+        }
+        double* X = sX + (g & 1) * C::XB;
+        X[2 * x_item] = acc.re;
+        X[2 * x_item + 1] = acc.im;
+    };
+
+    // ---- P chunk: P[(nl,i,j,re/im)][(el,c)] = sum_u X[el][nl][i][u] conj(gradH[n][j][c][u])
+    const int p_item = wave * C::P_IPW + lane;
+    const bool p_lane = lane < C::P_IPW && p_item < C::P_ITEMS;
+    const int p_i = p_item % 3, p_c = (p_item / 3) % NORB, p_nl = (p_item / (3 * NORB)) % 2,
+              p_el = p_item / (6 * NORB);
+    auto produce_p = [&](int64_t g) {
+        if (g >= niter || !p_lane) return;
+        const int ch = (int)(g % C::NCHUNK), np = ch % C::NP;
+        const int n = 2 * np + p_nl;
+        const double* X = sX + (g & 1) * C::XB + 2 * ((p_el * 2 + p_nl) * 3 + p_i) * NORB;
+        T* P = sP + (g & 1) * (C::KR * C::NCP) + p_el * NORB + p_c;
+        const int kr0 = (p_nl * 3 + p_i) * 3 * 2;
+        if (n < NB) {
+            cd xr[NORB];
+#pragma unroll
+            for (int u = 0; u < NORB; ++u) xr[u] = cd{X[2 * u], X[2 * u + 1]};
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const double* Ac = sA + 2 * ((n * 3 + j) * C::NN + p_c * NORB);
+                cd p{0.0, 0.0};
+#pragma unroll
+                for (int u = 0; u < NORB; ++u) cfma_conj(p, xr[u], cd{Ac[2 * u], Ac[2 * u + 1]});
+                P[(kr0 + 2 * j) * C::NCP] = T(p.re);
+                P[(kr0 + 2 * j + 1) * C::NCP] = T(p.im);
+            }
+        } else {
+#pragma unroll
+            for (int x = 0; x < 6; ++x) P[(kr0 + x) * C::NCP] = T(0);
+        }
+    };
+
+    // ---- matrix-core work of this wave: its own M-tile against every N-tile, plus
+    // at most one extra (M-tile, N-tile) pair from the M-tiles past the eighth
+    const bool has_own = wave < C::OWN;
+    const bool has_extra = wave < C::XP;
+    const int own_mt = wave;
+    const int ext_mt = C::WAVES + (C::XP > 0 ? wave / C::NT : 0);
+    const int ext_nt = C::XP > 0 ? wave % C::NT : 0;
+    auto row_info = [&](int mt, int& k, int& base, bool& neg, bool& pad) {
+        const int row = 16 * mt + j16;
+        pad = row >= C::MROWS;
+        const int rho = row & 1, kw = row >> 1;
+        k = pad ? 0 : kw / NW;
+        // real embedding [[Dr, -Di], [Di, Dr]]: the (re row, im column) entry is negated
+        neg = !pad && rho == 0 && kap == 1;
+        base = (pad ? 0 : (kw % NW) * C::WS) + (rho ^ kap) - kap + kk;
+    };
+    int own_k, own_base, ext_k, ext_base;
+    bool own_neg, ext_neg;
+    bool own_pad, ext_pad;
+    row_info(own_mt, own_k, own_base, own_neg, own_pad);
+    row_info(ext_mt, ext_k, ext_base, ext_neg, ext_pad);
+
+    // fp64 accumulators of the energy block (for fp32 operands the matrix cores
+    // accumulate one K chunk in fp32, which is then added here)
+    f64x4 acc[C::NT];
+    f64x4 acc_x = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int nt = 0; nt < C::NT; ++nt) acc[nt] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+    auto a_ptr = [&](int k, int base, bool pad, int kp, int np) -> const T* {
+        const int q = (k - kp + NKZ) % NKZ;
+        return sD + (pad ? C::ZOFF : q * C::QS) + base + np * 36;
+    };
+    auto mfma_chunk = [&](int64_t g) {
+        const int ch = (int)(g % C::NCHUNK), kp = ch / C::NP, np = ch % C::NP;
+        const T* Pb = sP + (g & 1) * (C::KR * C::NCP) + kk * C::NCP + j16;
+        if (has_own) {
+            const T* Ab = a_ptr(own_k, own_base, own_pad, kp, np);
+            if constexpr (PREC == SSE_FP64) {
+#pragma unroll
+                for (int ks = 0; ks < C::KS; ++ks) {
+                    const T av = O::neg_if(Ab[4 * ks], own_neg);
+#pragma unroll
+                    for (int nt = 0; nt < C::NT; ++nt) acc[nt] = O::mma(av, Pb[4 * ks * C::NCP + 16 * nt], acc[nt]);
+                }
+            } else {
+                typename O::Acc part[C::NT];
+#pragma unroll
+                for (int nt = 0; nt < C::NT; ++nt) part[nt] = typename O::Acc{0, 0, 0, 0};
+#pragma unroll
+                for (int ks = 0; ks < C::KS; ++ks) {
+                    const T av = O::neg_if(Ab[4 * ks], own_neg);
+#pragma unroll
+                    for (int nt = 0; nt < C::NT; ++nt) part[nt] = O::mma(av, Pb[4 * ks * C::NCP + 16 * nt], part[nt]);
+                }
+#pragma unroll
+                for (int nt = 0; nt < C::NT; ++nt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[nt][v] += (double)part[nt][v];
+            }
+        }
+        if (has_extra) {
+            const T* Ab = a_ptr(ext_k, ext_base, ext_pad, kp, np);
+            if constexpr (PREC == SSE_FP64) {
+#pragma unroll
+                for (int ks = 0; ks < C::KS; ++ks)
+                    acc_x = O::mma(O::neg_if(Ab[4 * ks], ext_neg), Pb[4 * ks * C::NCP + 16 * ext_nt], acc_x);
+            } else {
+                typename O::Acc part{0, 0, 0, 0};
+#pragma unroll
+                for (int ks = 0; ks < C::KS; ++ks)
+                    part = O::mma(O::neg_if(Ab[4 * ks], ext_neg), Pb[4 * ks * C::NCP + 16 * ext_nt], part);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc_x[v] += (double)part[v];
+            }
+        }
+    };
+
+    // ---- add one V tile of energy block blk into the output ring
+    auto scatter_tile = [&](int64_t blk, int mt, int nt, const f64x4& v4) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = 16 * mt + O::row_of(lane, v);
+            const int col = 16 * nt + j16;
+            if (row < C::MROWS && col < C::NCOLS) {
+                const int rho = row & 1, kw = row >> 1, k = kw / NW, w = kw % NW + 1;
+                const int el = col / NORB, c = col % NORB;
+                const int64_t es = blk * EB + el;
+                if (es < NE) {
+                    const int64_t lo = es - w, hi = es + w;
+                    const int off = (k * NORB + c) * 2 + rho;
+                    if (lo >= 0) atomicAdd(&sR[(int)(lo % C::RING) * C::RP + off], v4[v]);
+                    if (hi < NE) atomicAdd(&sR[(int)(hi % C::RING) * C::RP + off], v4[v]);
+                }
+            }
+        }
+    };
+    auto scatter = [&](int64_t blk) {
+        if (has_own) {
+#pragma unroll
+            for (int nt = 0; nt < C::NT; ++nt) {
+                scatter_tile(blk, own_mt, nt, acc[nt]);
+                acc[nt] = f64x4{0.0, 0.0, 0.0, 0.0};
+            }
+        }
+        if (has_extra) {
+            scatter_tile(blk, ext_mt, ext_nt, acc_x);
+            acc_x = f64x4{0.0, 0.0, 0.0, 0.0};
+        }
+    };
+
+    // ---- scale by alpha and store output planes [e_lo, e_hi); clear their ring slots
+    auto write_planes = [&](int64_t e_lo, int64_t e_hi) {
+        if (e_lo < 0) e_lo = 0;
+        if (e_hi > NE) e_hi = NE;
+        const int per = NKZ * NORB;
+        for (int64_t x = tid; x < (e_hi - e_lo) * per; x += C::THREADS) {
+            const int64_t e = e_lo + x / per;
+            const int kc = (int)(x % per), k = kc / NORB, c = kc % NORB;
+            double* slot = sR + (int)(e % C::RING) * C::RP + kc * 2;
+            const cd v{slot[0], slot[1]};
+            slot[0] = 0.0;
+            slot[1] = 0.0;
+            cstore(S, off_S(d, k, e, a) + r * NORB + c, cmul(alpha, v));
+        }
+    };
+
+    // ---- prologue: X for chunks 0 and 1, P for chunk 0
+    __syncthreads();
+    gather_g(0);
+    finish_x(0);
+    __syncthreads();
+    gather_g(1);
+    produce_p(0);
+    finish_x(1);
+    __syncthreads();
+
+    // ---- main loop: one barrier per chunk
+    const bool mfma_first = wave < 4;  // waves w and w+4 share a SIMD
+    for (int64_t g = 0; g < niter; ++g) {
+        gather_g(g + 2);  // G loads in flight under this chunk's matrix work
+        if (mfma_first) {
+            mfma_chunk(g);
+            produce_p(g + 1);
+        } else {
+            produce_p(g + 1);
+            mfma_chunk(g);
+        }
+        finish_x(g + 2);
+        if ((g % C::NCHUNK) == C::NCHUNK - 1) {
+            const int64_t blk = g / C::NCHUNK;
+            // fixed wave order keeps the fp64 sums bitwise reproducible
+            for (int w = 0; w < C::WAVES; ++w) {
+                if (wave == w) scatter(blk);
+                __syncthreads();
+            }
+            write_planes(blk * EB - NW, (blk + 1) * EB - NW);
+        }
+        __syncthreads();
+    }
+    write_planes(nblk * EB - NW, NE);
+}
+
+template <int NORB, int NKZ, int NW, int NB, int EB, int PREC>
+static hipError_t launch_fwd(const Dims& d, const double* G, const double* D, const double* A, const int32_t* nbr,
+                             cd alpha, double* S, hipStream_t stream) {
+    using C = Fwd64<NORB, NKZ, NW, NB, EB, PREC>;
+    auto kern = fwd_mfma_kernel<NORB, NKZ, NW, NB, EB, PREC>;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)C::LDS_BYTES);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const int64_t groups = ((d.na + 7) / 8) * 8 * NORB;
+    hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(C::THREADS), C::LDS_BYTES, stream, d, G, D, A, nbr, alpha, S);
+    return hipGetLastError();
+}
+
+bool fwd_mfma_specialised(const Dims& d) {
+    return (d.norb == 10 && d.nkz == 7 && d.nw == 10 && d.nb == 4) || (d.norb == 4 && d.nkz == 3 && d.nw == 2 && d.nb == 4) ||
+           (d.norb == 10 && d.nkz == 7 && d.nw == 10 && d.nb == 3);
+}
+
+template <int PREC>
+static hipError_t dispatch_fwd(const Dims& d, const double* G, const double* D, const double* A, const int32_t* nbr,
+                               cd alpha, double* S, hipStream_t stream) {
+    if (d.norb == 10 && d.nkz == 7 && d.nw == 10 && d.nb == 4)
+        return launch_fwd<10, 7, 10, 4, 8, PREC>(d, G, D, A, nbr, alpha, S, stream);
+    if (d.norb == 10 && d.nkz == 7 && d.nw == 10 && d.nb == 3)
+        return launch_fwd<10, 7, 10, 3, 8, PREC>(d, G, D, A, nbr, alpha, S, stream);
+    if (d.norb == 4 && d.nkz == 3 && d.nw == 2 && d.nb == 4)
+        return launch_fwd<4, 3, 2, 4, 8, PREC>(d, G, D, A, nbr, alpha, S, stream);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_fwd_mfma(const Dims& d, int precision, const double* G, const double* D, const double* A,
+                           const int32_t* nbr, cd alpha, double* S, hipStream_t stream) {
+    if (precision == SSE_FP64) return dispatch_fwd<SSE_FP64>(d, G, D, A, nbr, alpha, S, stream);
+    if (precision == SSE_FP32) return dispatch_fwd<SSE_FP32>(d, G, D, A, nbr, alpha, S, stream);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace sse

@@ -10,10 +10,10 @@ bool generic_supported(const Dims& d);
 hipError_t launch_fwd_generic(const Dims& d, const double* G, const double* D, const double* A, const int32_t* nbr,
                               cd alpha, double* S, hipStream_t stream);
 
-// fp64 matrix-core forward for the shapes it is instantiated for
-bool fwd64_specialised(const Dims& d);
-hipError_t launch_fwd_mfma64(const Dims& d, const double* G, const double* D, const double* A, const int32_t* nbr,
-                             cd alpha, double* S, hipStream_t stream);
+// matrix-core forward (fp64 or fp32 operands) for the shapes it is instantiated for
+bool fwd_mfma_specialised(const Dims& d);
+hipError_t launch_fwd_mfma(const Dims& d, int precision, const double* G, const double* D, const double* A,
+                           const int32_t* nbr, cd alpha, double* S, hipStream_t stream);
 
 // neighbour-table range check: sets *flag (device int) to 1 if any entry is outside [0, na)
 hipError_t launch_check_nbr(const Dims& d, const int32_t* nbr, int* flag, hipStream_t stream);

@@ -1,0 +1,75 @@
+"""Reduced-precision forms of the forward against the fp64 oracle (GPU).
+
+Every form reads the same fp64 inputs, gathers them in fp64 and reduces over
+(qz, w, +/-) in fp64; only the operands of the dense products are rounded.
+Each test prints the measured error so that the log reports it for every
+result; the bar is the 1e-6 relative Frobenius error targeted for the
+mixed-precision form.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle
+from paper_1912_10024_amd import sse
+from paper_1912_10024_amd.inputs import CONFIGS, Dims, generate, make_nbr, anti_hermitian_blocks
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-6}
+
+
+def _rand(dims: Dims, seed: int):
+    rng = np.random.default_rng(seed)
+
+    def cn(shape, s=1.0):
+        return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) * s
+
+    return dict(G=anti_hermitian_blocks(cn(dims.g_shape)), D=cn(dims.d_shape), dH=cn(dims.dh_shape, 0.1),
+                nbr=make_nbr(rng, dims.na, dims.nb))
+
+
+def _errs(S, ref):
+    rel = float(np.linalg.norm(S - ref) / np.linalg.norm(ref))
+    blk = np.linalg.norm((S - ref).reshape(-1, S.shape[-2] * S.shape[-1]), axis=1) / np.maximum(
+        np.linalg.norm(ref.reshape(-1, S.shape[-2] * S.shape[-1]), axis=1), 1e-300)
+    return rel, float(blk.max()), float(np.max(np.abs(S - ref)) / np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("precision", sorted(TOL))
+@pytest.mark.parametrize("dims,seed", [
+    (CONFIGS["tiny"], 0),
+    (Dims(nkz=7, ne=29, nqz=7, nw=10, na=6, nb=4, norb=10, g_slots=5), 1),
+    (Dims(nkz=7, ne=17, nqz=7, nw=10, na=5, nb=3, norb=10, g_slots=1), 2),
+], ids=["tiny", "ragged", "odd_nb"])
+def test_reduced_precision_error(precision, dims, seed):
+    inp = _rand(dims, seed)
+    t = {k: torch.from_numpy(v).cuda() for k, v in inp.items()}
+    S = sse.forward(t["G"], t["D"], t["dH"], t["nbr"], alpha=1j, precision=precision).cpu().numpy()
+    ref = oracle.sse_forward(dims, inp["G"], inp["D"], inp["dH"], inp["nbr"], alpha=1j)
+    rel, blk, mx = _errs(S, ref)
+    print(f"[precision] {precision} dims={dims.as_tuple()} rel_frob={rel:.3e} max_block_rel={blk:.3e} max_abs_rel={mx:.3e}")
+    assert rel <= TOL[precision]
+    assert rel > 1e-12  # the form really computes in reduced precision
+
+
+@pytest.mark.parametrize("precision", sorted(TOL))
+def test_reduced_precision_mid_sampled(precision):
+    d = CONFIGS["mid"]
+    inp = generate(d, 1)
+    t = {k: torch.from_numpy(inp[k]).cuda() for k in ("G<", "D<", "dH", "nbr")}
+    S = sse.forward(t["G<"], t["D<"], t["dH"], t["nbr"], precision=precision)
+    rng = np.random.default_rng(5)
+    pts = [tuple(int(x) for x in (rng.integers(d.nkz), rng.integers(d.ne), rng.integers(d.na))) for _ in range(24)]
+    ref = oracle.sse_points(d, inp["G<"], inp["D<"], inp["dH"], inp["nbr"], pts)
+    got = np.stack([S[k, e, a].cpu().numpy() for k, e, a in pts])
+    rel, blk, mx = _errs(got, ref)
+    print(f"[precision] {precision} mid sampled rel_frob={rel:.3e} max_block_rel={blk:.3e}")
+    assert rel <= TOL[precision]
+
+
+def test_unknown_precision_rejected():
+    d = CONFIGS["tiny"]
+    t = {k: torch.from_numpy(v).cuda() for k, v in _rand(d, 0).items()}
+    with pytest.raises(ValueError):
+        sse.forward(t["G"], t["D"], t["dH"], t["nbr"], precision="fp8")
