@@ -36,9 +36,12 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--config", default="device", choices=["tiny", "mid", "device"])
-    p.add_argument("--precision", default="fp64")
+    p.add_argument("--forms", default="fp64,fp32",
+                   help="comma-separated operand precisions to time; the first is the headline value")
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle baseline sample")
     p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
+                   help="only run a plain device copy of this many GiB (scales HBM byte counters)")
     return p.parse_args()
 
 
@@ -65,9 +68,9 @@ def compact_problem(d, G, D, dH, nbr, atoms):
     return sub, np.ascontiguousarray(Gs), np.ascontiguousarray(Ds), np.ascontiguousarray(Hs), nb_s, remap
 
 
-def cpu_baseline(d, G, D, dH, nbr, S, target_s, f_block, seed=7):
+def cpu_baseline(d, G, D, dH, nbr, outputs, target_s, f_block, seed=7):
     """Time the CPU oracle on a bounded sample of output blocks of this workload
-    and check those blocks against the GPU result."""
+    and check those blocks against every GPU form."""
     from oracle import oracle
 
     rng = np.random.default_rng(seed)
@@ -82,26 +85,48 @@ def cpu_baseline(d, G, D, dH, nbr, S, target_s, f_block, seed=7):
         return [(int(k), int(e), int(a)) for k, e, a in zip(ks, es, aa)]
 
     # calibrate, then run a sample sized to target_s
-    cal = pts_for(8)
+    cal = pts_for(16)
     t0 = time.perf_counter()
     oracle.sse_points(sub, Gs, Ds, Hs, nbs, [(k, e, remap[a]) for k, e, a in cal])
     per = (time.perf_counter() - t0) / len(cal)
-    n = int(max(8, min(4096, target_s / max(per, 1e-6))))
+    n = int(max(16, min(200000, target_s / max(per, 1e-6))))
     pts = pts_for(n)
     t0 = time.perf_counter()
     ref = oracle.sse_points(sub, Gs, Ds, Hs, nbs, [(k, e, remap[a]) for k, e, a in pts])
     t = time.perf_counter() - t0
-    got = np.stack([S[k, e, a].cpu().numpy() for k, e, a in pts])
-    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    errs = {}
+    import torch
+    idx = torch.tensor(pts, device=G.device)
+    for form, S in outputs.items():
+        got = S[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy()
+        errs[form] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
     return {
         "value": n * f_block / t / 1e12,
         "unit": "TFLOP/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": f"{n} output blocks Sigma[kz,E,a] (4 seeded atoms, random kz,E) of the same workload, {t:.1f} s",
+        "sample": f"{n} output blocks Sigma[kz,E,a] of the same workload (4 seeded atoms, random kz and E), {t:.1f} s",
         "seconds": t,
-        "gpu_vs_oracle_rel_err": err,
-    }
+    }, errs
+
+
+def time_form(sse, G, D, dH, nbr, S, ws, form, steps, warmup, dev):
+    import torch
+
+    for _ in range(warmup):
+        sse.forward(G, D, dH, nbr, precision=form, out=S, ws=ws)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        ev[s][0].record(stream)
+        sse.forward(G, D, dH, nbr, precision=form, out=S, ws=ws)
+        ev[s][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, [a.elapsed_time(b) for a, b in ev]
 
 
 def main():
@@ -112,68 +137,81 @@ def main():
         sys.exit(2)
     import torch
 
+    if args.copy_calibration > 0:
+        n = int(args.copy_calibration * (1 << 30)) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n}), flush=True)
+        return
+
     from paper_1912_10024_amd import flops, sse
     from paper_1912_10024_amd.inputs import CONFIGS, CONFIG_INDEX, generate_device
 
     d = CONFIGS[args.config]
     dev = torch.device("cuda:0")
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     t_gen = time.perf_counter()
     inp = generate_device(d, CONFIG_INDEX[args.config], device=dev)
     G, D, dH, nbr = inp["G<"], inp["D<"], inp["dH"], inp["nbr"]
     sse.check_nbr(nbr, d.na)
-    S = torch.empty(d.sigma_shape, dtype=torch.complex128, device=dev)
-    ws = sse.workspace(d, args.precision, device=dev)
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t_gen
 
-    for _ in range(args.warmup):
-        sse.forward(G, D, dH, nbr, precision=args.precision, out=S, ws=ws)
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream(dev)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        ev[s][0].record(stream)
-        sse.forward(G, D, dH, nbr, precision=args.precision, out=S, ws=ws)
-        ev[s][1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kern_ms = [a.elapsed_time(b) for a, b in ev]
-    ms = float(np.mean(kern_ms))
     f_eff = flops.f_eff(d)
     gemm = flops.pd_gemm_flops(d)
-    value = f_eff / (ms * 1e-3) / 1e12
-    peak = {"fp64": FP64_MFMA_PEAK, "fp32": FP32_MFMA_PEAK, "bf16x3": BF16_MFMA_PEAK}[args.precision]
-    achieved = gemm / (ms * 1e-3)
+    peaks = {"fp64": FP64_MFMA_PEAK, "fp32": FP32_MFMA_PEAK, "bf16x3": BF16_MFMA_PEAK}
+    outputs, res = {}, {}
+    for form in forms:
+        S = torch.empty(d.sigma_shape, dtype=torch.complex128, device=dev)
+        ws = sse.workspace(d, form, device=dev)
+        wall, kern_ms = time_form(sse, G, D, dH, nbr, S, ws, form, args.steps, args.warmup, dev)
+        ms = float(np.mean(kern_ms))
+        achieved = gemm / (ms * 1e-3)
+        res[form] = {
+            "value": f_eff / (ms * 1e-3) / 1e12,
+            "ms_per_step": wall * 1e3 / args.steps,
+            "kernel_ms": ms,
+            "kernel_ms_all": [round(x, 3) for x in kern_ms],
+            "roofline": {"bound": "mfma", "achieved": round(achieved / 1e12, 3), "peak": peaks[form] / 1e12,
+                         "unit": "TFLOP/s", "frac": round(achieved / peaks[form], 4), "traffic": None,
+                         "flops_per_launch": gemm, "what": f"dense P.D GEMM flops on {form} matrix cores"},
+        }
+        outputs[form] = S
+    head = forms[0]
     line = {
-        "metric": "SSE effective TFLOP/s (fp64, one Sigma component)",
-        "value": round(value, 3),
+        "metric": "SSE effective TFLOP/s (paper's regrouped flop count, one Sigma component), fp64 vs mixed",
+        "value": round(res[head]["value"], 3),
         "unit": "TFLOP/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(wall * 1e3 / args.steps, 3),
+        "ms_per_step": round(res[head]["ms_per_step"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else args.precision,
+        "dtype": "f64" if head == "fp64" else head,
         "data": "synthetic",
-        "config": {"workload": f"electron-phonon SSE Sigma^< forward, {args.config}",
+        "config": {"workload": f"electron-phonon SSE Sigma^< forward ({args.config})",
                    "nkz": d.nkz, "ne": d.ne, "nqz": d.nqz, "nw": d.nw, "na": d.na, "nb": d.nb,
-                   "norb": d.norb, "g_slots": d.g_slots, "precision": args.precision},
-        "kernel_ms": round(ms, 3),
-        "kernel_ms_all": [round(x, 3) for x in kern_ms],
+                   "norb": d.norb, "g_slots": d.g_slots},
+        "kernel_ms": round(res[head]["kernel_ms"], 3),
         "f_eff": f_eff,
-        "roofline": {"bound": "mfma", "achieved": round(achieved / 1e12, 3), "peak": peak / 1e12,
-                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-                     "flops_per_launch": gemm, "what": "dense P.D GEMM flops on matrix cores"},
+        "roofline": res[head]["roofline"],
         "executed_flops_per_launch": flops.pd_executed_flops(d),
         "input_gen_s": round(t_gen, 2),
+        "forms": {f: {"value": round(r["value"], 3), "kernel_ms": round(r["kernel_ms"], 3),
+                      "kernel_ms_all": r["kernel_ms_all"], "mfma_frac": r["roofline"]["frac"],
+                      "speedup_vs_" + head: round(res[head]["kernel_ms"] / r["kernel_ms"], 3)}
+                  for f, r in res.items()},
     }
     if not args.no_cpu:
         f_block = f_eff / (d.nkz * d.ne * d.na)
-        line["cpu_baseline"] = cpu_baseline(d, G, D, dH, nbr, S, args.cpu_seconds, f_block)
+        cpu, errs = cpu_baseline(d, G, D, dH, nbr, outputs, args.cpu_seconds, f_block)
+        line["cpu_baseline"] = cpu
+        for f, e in errs.items():
+            line["forms"][f]["rel_err_vs_oracle_sampled"] = e
     print(json.dumps(line), flush=True)
 
 

@@ -76,6 +76,10 @@ int sse_workspace_bytes(const sse_dims* dims, int precision, int backward, size_
     if (!backward && precision != SSE_FP64 && precision != SSE_FP32 && precision != SSE_BF16X3)
         return fail(SSE_ERR_PRECISION, "unknown precision %d", precision);
     size_t ws = 256;  // status flag of sse_check_nbr
+    if (backward) {
+        const size_t b = sse::bwd_workspace_bytes(sse::to_dims(*dims));
+        if (b > ws) ws = b;
+    }
     *bytes = ws;
     return ok();
 }
@@ -124,8 +128,17 @@ int sse_backward(const sse_dims* dims, const double* G, const double* D, const d
     int rc = check_dims(dims);
     if (rc) return rc;
     if (!G || !D || !dH || !nbr || !dSigma) return fail(SSE_ERR_NULL, "an input pointer is NULL");
-    (void)alpha_re; (void)alpha_im; (void)dG; (void)dD; (void)ddH; (void)workspace; (void)workspace_bytes; (void)stream;
-    return fail(SSE_ERR_DIMS, "backward not built yet");
+    const sse::Dims d = sse::to_dims(*dims);
+    if (!sse::bwd_supported(d)) return fail(SSE_ERR_DIMS, "no adjoint kernel for these dims");
+    size_t need = 0;
+    sse_workspace_bytes(dims, SSE_FP64, 1, &need);
+    if (workspace == nullptr || workspace_bytes < need)
+        return fail(SSE_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace_bytes);
+    if (!dG && !dD && !ddH) return ok();
+    hipError_t e = sse::launch_bwd(d, G, D, dH, nbr, sse::cd{alpha_re, alpha_im}, dSigma, dG, dD, ddH, workspace,
+                                   reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "backward launch");
+    return ok();
 }
 
 int sse_check_nbr(const sse_dims* dims, const int32_t* nbr, void* workspace, size_t workspace_bytes, void* stream) {

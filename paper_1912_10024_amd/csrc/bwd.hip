@@ -1,0 +1,360 @@
+// Adjoint of the scattering self-energy (fp64, vector ALUs).
+//
+// With g = dL/dSigma (PyTorch's complex-gradient convention) define, for an
+// edge (a, n) with neighbour b = nbr[a,n] and a source point (k', E'):
+//   W_{q,w}[k',E'] = g[(k'+q) mod Nkz, E'+w, a] + g[(k'+q) mod Nkz, E'-w, a]   (0 outside the grid)
+//   Y_ij[k',E']    = conj(alpha) sum_{q,w} conj(D[q,w-1,a,n,i,j]) W_{q,w}[k',E']
+// (the adjoint of the (qz, w, +/-) stencil and of the D contraction), and with
+// B = G[k',E',b,0], P_ij = grad_i H . B . grad_j H^H:
+//   dG[k',E',b,0]   += sum_ij grad_i H^H . Y_ij . grad_j H
+//   d gradH[a,n,m]  += sum_j Y_mj . (grad_j H . B^H) + sum_i Y_im^H . (grad_i H . B)
+//   dD[q,w-1,a,n,ij] = conj(alpha) sum_{k',E'} sum_rc conj(P_ij[rc]) W_{q,w}[rc]
+// Shifted blocks are re-gathered from G and g, nothing of the forward is stored.
+//
+// dG and d gradH are formed by one workgroup per neighbour atom b, which walks
+// the edges that point at b (a reverse adjacency built in the workspace, in
+// edge order), so every output element has one owner: no atomics, bitwise
+// reproducible.  dD is formed by one workgroup per edge.
+#include "sse_kernels.h"
+
+namespace sse {
+
+namespace {
+constexpr int kBwdThreads = 256;
+}
+
+// ---------------------------------------------------------------- reverse adjacency
+// ws layout (int32): count[na] | offset[na+1] | cursor[na] | edges[na*nb]
+__global__ void rcsr_count_kernel(int64_t na, int64_t nb, const int32_t* __restrict__ nbr, int32_t* count) {
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < na * nb; x += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t b = nbr[x];
+        if (b >= 0 && b < na) atomicAdd(&count[b], 1);
+    }
+}
+
+// single workgroup exclusive scan (na is at most a few hundred thousand)
+__global__ void rcsr_scan_kernel(int64_t na, const int32_t* __restrict__ count, int32_t* offset, int32_t* cursor) {
+    __shared__ int32_t part[1024];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int64_t per = (na + nt - 1) / nt;
+    const int64_t lo = tid * per, hi = (lo + per < na) ? lo + per : na;
+    int32_t s = 0;
+    for (int64_t i = lo; i < hi; ++i) s += count[i];
+    part[tid] = s;
+    __syncthreads();
+    if (tid == 0) {
+        int32_t run = 0;
+        for (int t = 0; t < nt; ++t) {
+            const int32_t v = part[t];
+            part[t] = run;
+            run += v;
+        }
+        offset[na] = run;
+    }
+    __syncthreads();
+    int32_t run = part[tid];
+    for (int64_t i = lo; i < hi; ++i) {
+        offset[i] = run;
+        cursor[i] = run;
+        run += count[i];
+    }
+}
+
+__global__ void rcsr_fill_kernel(int64_t na, int64_t nb, const int32_t* __restrict__ nbr, int32_t* cursor, int32_t* edges) {
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < na * nb; x += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t b = nbr[x];
+        if (b >= 0 && b < na) edges[atomicAdd(&cursor[b], 1)] = (int32_t)x;
+    }
+}
+
+// the fill order is arbitrary: sort each (short) list so the walk is in edge order
+__global__ void rcsr_sort_kernel(int64_t na, const int32_t* __restrict__ offset, int32_t* edges) {
+    for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < na; b += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t lo = offset[b], hi = offset[b + 1];
+        for (int32_t i = lo + 1; i < hi; ++i) {
+            const int32_t v = edges[i];
+            int32_t j = i - 1;
+            while (j >= lo && edges[j] > v) {
+                edges[j + 1] = edges[j];
+                --j;
+            }
+            edges[j + 1] = v;
+        }
+    }
+}
+
+__global__ void zero_i32_kernel(int64_t n, int32_t* p) {
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) p[x] = 0;
+}
+
+size_t bwd_workspace_bytes(const Dims& d) { return sizeof(int32_t) * (size_t)(3 * d.na + 1 + d.na * d.nb) + 256; }
+
+// --------------------------------------------------------------- W and Y of one source point
+// Thread x < NN accumulates Y_ij[x] for all nine (i,j) from the 2*Nqz*Nw shifted g blocks.
+__device__ __forceinline__ void compute_y(const Dims& d, const double* __restrict__ gS, int64_t a, int64_t kp,
+                                          int64_t ep, const cd* sDn, cd calpha, int x, cd* y) {
+#pragma unroll
+    for (int ij = 0; ij < 9; ++ij) y[ij] = cd{0.0, 0.0};
+    for (int64_t q = 0; q < d.nqz; ++q) {
+        const int64_t k = (kp + q) % d.nkz;
+        for (int64_t w = 1; w <= d.nw; ++w) {
+            cd wv{0.0, 0.0};
+            if (ep + w < d.ne) {
+                const cd v = cload(gS, off_S(d, k, ep + w, a) + x);
+                wv.re += v.re;
+                wv.im += v.im;
+            }
+            if (ep - w >= 0) {
+                const cd v = cload(gS, off_S(d, k, ep - w, a) + x);
+                wv.re += v.re;
+                wv.im += v.im;
+            }
+            const cd* dq = sDn + (q * d.nw + (w - 1)) * 9;
+#pragma unroll
+            for (int ij = 0; ij < 9; ++ij) cfma_conja(y[ij], dq[ij], wv);
+        }
+    }
+#pragma unroll
+    for (int ij = 0; ij < 9; ++ij) y[ij] = cmul(calpha, y[ij]);
+}
+
+// --------------------------------------------------------------- dG and d gradH
+__global__ __launch_bounds__(kBwdThreads) void bwd_dg_dh_kernel(Dims d, const double* __restrict__ G,
+                                                                const double* __restrict__ Dg,
+                                                                const double* __restrict__ Ag,
+                                                                const double* __restrict__ gS, cd calpha,
+                                                                const int32_t* __restrict__ offset,
+                                                                const int32_t* __restrict__ edges,
+                                                                double* __restrict__ dG, double* __restrict__ dA) {
+    extern __shared__ double smem[];
+    const int N = (int)d.norb, NN = N * N;
+    const int nqw = (int)(d.nqz * d.nw);
+    cd* sDn = reinterpret_cast<cd*>(smem);  // [q][w][ij]
+    cd* sA = sDn + nqw * 9;                 // [3][N][N]   grad H of the edge
+    cd* sY = sA + 3 * NN;                   // [9][N][N]
+    cd* sB = sY + 9 * NN;                   // [N][N]
+    cd* sT = sB + NN;                       // [3][N][N]   sum_i A_i^H Y_ij
+    cd* sC = sT + 3 * NN;                   // [3][N][N]   A_j B^H
+    cd* sE = sC + 3 * NN;                   // [3][N][N]   A_i B
+    cd* sdA = sE + 3 * NN;                  // [3][N][N]   accumulated d gradH of the edge
+    const int tid = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    if (b >= d.na) return;
+    const int32_t e_lo = offset[b], e_hi = offset[b + 1];
+
+    // slots >= 1 of dG are not read by the forward map: zero
+    if (dG && (d.gs > 1 || e_lo == e_hi)) {
+        for (int64_t kp = 0; kp < d.nkz; ++kp)
+            for (int64_t ep = 0; ep < d.ne; ++ep) {
+                const int64_t base = off_G(d, kp, ep, b);
+                const int64_t from = (e_lo == e_hi) ? 0 : NN;
+                for (int64_t x = from + tid; x < d.gs * NN; x += kBwdThreads) cstore(dG, base + x, cd{0.0, 0.0});
+            }
+    }
+    for (int32_t ei = e_lo; ei < e_hi; ++ei) {
+        const int32_t edge = edges[ei];
+        const int64_t a = edge / d.nb, n = edge % d.nb;
+        __syncthreads();
+        for (int x = tid; x < nqw * 9; x += kBwdThreads) {
+            const int ij = x % 9, qw = x / 9;
+            sDn[x] = cload(Dg, off_D(d, qw / d.nw, qw % d.nw, a, n) + ij);
+        }
+        for (int x = tid; x < 3 * NN; x += kBwdThreads) {
+            sA[x] = cload(Ag, off_A(d, a, n, 0) + x);
+            sdA[x] = cd{0.0, 0.0};
+        }
+        __syncthreads();
+        for (int64_t kp = 0; kp < d.nkz; ++kp)
+            for (int64_t ep = 0; ep < d.ne; ++ep) {
+                if (tid < NN) {
+                    cd y[9];
+                    compute_y(d, gS, a, kp, ep, sDn, calpha, tid, y);
+#pragma unroll
+                    for (int ij = 0; ij < 9; ++ij) sY[ij * NN + tid] = y[ij];
+                    sB[tid] = cload(G, off_G(d, kp, ep, b) + tid);
+                }
+                __syncthreads();
+                // T_j = sum_i A_i^H Y_ij ; C_j = A_j B^H ; E_i = A_i B
+                for (int x = tid; x < 9 * NN; x += kBwdThreads) {
+                    const int m = x / NN, rc = x % NN, r = rc / N, c = rc % N;
+                    cd s{0.0, 0.0};
+                    if (m < 3) {
+                        const int j = m;
+                        for (int i = 0; i < 3; ++i)
+                            for (int t = 0; t < N; ++t) cfma_conja(s, sA[i * NN + t * N + r], sY[(i * 3 + j) * NN + t * N + c]);
+                        sT[j * NN + rc] = s;
+                    } else if (m < 6) {
+                        const int j = m - 3;
+                        for (int t = 0; t < N; ++t) cfma_conj(s, sA[j * NN + r * N + t], sB[c * N + t]);
+                        sC[j * NN + rc] = s;
+                    } else {
+                        const int i = m - 6;
+                        for (int t = 0; t < N; ++t) cfma(s, sA[i * NN + r * N + t], sB[t * N + c]);
+                        sE[i * NN + rc] = s;
+                    }
+                }
+                __syncthreads();
+                // dG[k',E',b] (+)= sum_j T_j A_j
+                for (int x = tid; dG && x < NN; x += kBwdThreads) {
+                    const int t = x / N, u = x % N;
+                    cd s{0.0, 0.0};
+                    for (int j = 0; j < 3; ++j)
+                        for (int c = 0; c < N; ++c) cfma(s, sT[j * NN + t * N + c], sA[j * NN + c * N + u]);
+                    const int64_t o = off_G(d, kp, ep, b) + x;
+                    if (ei != e_lo) {
+                        const cd prev = cload(dG, o);
+                        s.re += prev.re;
+                        s.im += prev.im;
+                    }
+                    cstore(dG, o, s);
+                }
+                // d gradH_m += sum_j Y_mj C_j + sum_i Y_im^H E_i
+                for (int x = tid; dA && x < 3 * NN; x += kBwdThreads) {
+                    const int m = x / NN, rc = x % NN, r = rc / N, c = rc % N;
+                    cd s = sdA[x];
+                    for (int j = 0; j < 3; ++j)
+                        for (int t = 0; t < N; ++t) cfma(s, sY[(m * 3 + j) * NN + r * N + t], sC[j * NN + t * N + c]);
+                    for (int i = 0; i < 3; ++i)
+                        for (int t = 0; t < N; ++t) cfma_conja(s, sY[(i * 3 + m) * NN + t * N + r], sE[i * NN + t * N + c]);
+                    sdA[x] = s;
+                }
+                __syncthreads();
+            }
+        for (int x = tid; dA && x < 3 * NN; x += kBwdThreads) cstore(dA, off_A(d, a, n, 0) + x, sdA[x]);
+    }
+}
+
+// --------------------------------------------------------------- dD
+__global__ __launch_bounds__(kBwdThreads) void bwd_dd_kernel(Dims d, const double* __restrict__ G,
+                                                             const double* __restrict__ Ag,
+                                                             const int32_t* __restrict__ nbr,
+                                                             const double* __restrict__ gS, cd calpha,
+                                                             double* __restrict__ dD) {
+    extern __shared__ double smem[];
+    const int N = (int)d.norb, NN = N * N;
+    const int nqw = (int)(d.nqz * d.nw);
+    cd* sA = reinterpret_cast<cd*>(smem);  // [3][N][N]
+    cd* sB = sA + 3 * NN;                  // [N][N]
+    cd* sE = sB + NN;                      // [3][N][N]  A_i B
+    cd* sP = sE + 3 * NN;                  // [9][N][N]  A_i B A_j^H
+    const int tid = threadIdx.x;
+    const int64_t edge = blockIdx.x;
+    if (edge >= d.na * d.nb) return;
+    const int64_t a = edge / d.nb, n = edge % d.nb;
+    const int32_t b = nbr[edge];
+    for (int x = tid; x < 3 * NN; x += kBwdThreads) sA[x] = cload(Ag, off_A(d, a, n, 0) + x);
+    // each thread owns up to two (q, w) pairs and accumulates all nine (i,j)
+    constexpr int kPer = 2;
+    cd acc[kPer][9];
+#pragma unroll
+    for (int s = 0; s < kPer; ++s)
+#pragma unroll
+        for (int ij = 0; ij < 9; ++ij) acc[s][ij] = cd{0.0, 0.0};
+    const bool valid_b = b >= 0 && b < d.na;
+    for (int64_t kp = 0; kp < d.nkz; ++kp)
+        for (int64_t ep = 0; ep < d.ne; ++ep) {
+            __syncthreads();
+            for (int x = tid; x < NN; x += kBwdThreads) sB[x] = valid_b ? cload(G, off_G(d, kp, ep, b) + x) : cd{0.0, 0.0};
+            __syncthreads();
+            for (int x = tid; x < 3 * NN; x += kBwdThreads) {
+                const int i = x / NN, r = (x % NN) / N, c = x % N;
+                cd s{0.0, 0.0};
+                for (int t = 0; t < N; ++t) cfma(s, sA[i * NN + r * N + t], sB[t * N + c]);
+                sE[x] = s;
+            }
+            __syncthreads();
+            for (int x = tid; x < 9 * NN; x += kBwdThreads) {
+                const int ij = x / NN, i = ij / 3, j = ij % 3, r = (x % NN) / N, c = x % N;
+                cd s{0.0, 0.0};
+                for (int u = 0; u < N; ++u) cfma_conj(s, sE[i * NN + r * N + u], sA[j * NN + c * N + u]);
+                sP[x] = s;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int s = 0; s < kPer; ++s) {
+                const int qw = tid + s * kBwdThreads;
+                if (qw < nqw) {
+                    const int64_t q = qw / d.nw, w = qw % d.nw + 1;
+                    const int64_t k = (kp + q) % d.nkz;
+                    const bool hi = ep + w < d.ne, lo = ep - w >= 0;
+                    const double* g1 = gS + 2 * off_S(d, k, hi ? ep + w : ep, a);
+                    const double* g2 = gS + 2 * off_S(d, k, lo ? ep - w : ep, a);
+                    for (int rc = 0; rc < NN; ++rc) {
+                        cd wv{0.0, 0.0};
+                        if (hi) {
+                            const cd v = cload(g1, rc);
+                            wv.re += v.re;
+                            wv.im += v.im;
+                        }
+                        if (lo) {
+                            const cd v = cload(g2, rc);
+                            wv.re += v.re;
+                            wv.im += v.im;
+                        }
+#pragma unroll
+                        for (int ij = 0; ij < 9; ++ij) cfma_conja(acc[s][ij], sP[ij * NN + rc], wv);
+                    }
+                }
+            }
+        }
+#pragma unroll
+    for (int s = 0; s < kPer; ++s) {
+        const int qw = tid + s * kBwdThreads;
+        if (qw < nqw) {
+            const int64_t q = qw / d.nw, w = qw % d.nw;
+#pragma unroll
+            for (int ij = 0; ij < 9; ++ij) cstore(dD, off_D(d, q, w, a, n) + ij, cmul(calpha, acc[s][ij]));
+        }
+    }
+}
+
+static size_t bwd_lds_dg(const Dims& d) {
+    const size_t NN = (size_t)(d.norb * d.norb);
+    return sizeof(cd) * ((size_t)d.nqz * d.nw * 9 + 3 * NN + 9 * NN + NN + 4 * 3 * NN);
+}
+static size_t bwd_lds_dd(const Dims& d) {
+    const size_t NN = (size_t)(d.norb * d.norb);
+    return sizeof(cd) * (3 * NN + NN + 3 * NN + 9 * NN);
+}
+
+bool bwd_supported(const Dims& d) {
+    return d.nqz * d.nw <= 2 * kBwdThreads && d.norb * d.norb <= kBwdThreads && bwd_lds_dg(d) <= 160 * 1024 &&
+           bwd_lds_dd(d) <= 160 * 1024 && d.na * d.nb <= INT32_MAX;
+}
+
+hipError_t launch_bwd(const Dims& d, const double* G, const double* D, const double* A, const int32_t* nbr, cd alpha,
+                      const double* gS, double* dG, double* dD, double* dA, void* ws, hipStream_t stream) {
+    const cd calpha{alpha.re, -alpha.im};
+    if (dG || dA) {
+        int32_t* count = reinterpret_cast<int32_t*>(ws);
+        int32_t* offset = count + d.na;
+        int32_t* cursor = offset + d.na + 1;
+        int32_t* edges = cursor + d.na;
+        const unsigned g1 = (unsigned)((d.na * d.nb + 255) / 256 < 4096 ? (d.na * d.nb + 255) / 256 : 4096);
+        hipLaunchKernelGGL(zero_i32_kernel, dim3(g1), dim3(256), 0, stream, d.na, count);
+        hipLaunchKernelGGL(rcsr_count_kernel, dim3(g1), dim3(256), 0, stream, d.na, d.nb, nbr, count);
+        hipLaunchKernelGGL(rcsr_scan_kernel, dim3(1), dim3(1024), 0, stream, d.na, count, offset, cursor);
+        hipLaunchKernelGGL(rcsr_fill_kernel, dim3(g1), dim3(256), 0, stream, d.na, d.nb, nbr, cursor, edges);
+        const unsigned g2 = (unsigned)((d.na + 255) / 256 < 4096 ? (d.na + 255) / 256 : 4096);
+        hipLaunchKernelGGL(rcsr_sort_kernel, dim3(g2), dim3(256), 0, stream, d.na, offset, edges);
+        const size_t lds = bwd_lds_dg(d);
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(bwd_dg_dh_kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(bwd_dg_dh_kernel, dim3((unsigned)d.na), dim3(kBwdThreads), lds, stream, d, G, D, A, gS, calpha,
+                           offset, edges, dG, dA);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (dD) {
+        const size_t lds = bwd_lds_dd(d);
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(bwd_dd_kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(bwd_dd_kernel, dim3((unsigned)(d.na * d.nb)), dim3(kBwdThreads), lds, stream, d, G, A, nbr, gS,
+                           calpha, dD);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace sse

@@ -98,10 +98,17 @@ struct Fwd64 {
     static constexpr size_t LDS_BYTES = sizeof(double) * (size_t)(OPER_DOUBLES + L_A + L_X + L_R);
     static constexpr int X_ITEMS = EB * 2 * 3 * NORB;  // (el, nl, i, u)
     static constexpr int X_IPW = (X_ITEMS + WAVES - 1) / WAVES;
-    static constexpr int P_ITEMS = EB * 2 * NORB * 3;  // (el, nl, c, i)
-    static constexpr int P_IPW = (P_ITEMS + WAVES - 1) / WAVES;
+    // P chunk on the matrix cores, per neighbour of the pair: C[(el,i,re/im), (j,c)] =
+    // sum_(u,re/im) X-embedding[(el,i,re/im), (u,re/im)] . conj(gradH[n][j][c][u]) parts
+    static constexpr int PM_ROWS = EB * 3 * 2;
+    static constexpr int PMT = (PM_ROWS + 15) / 16;
+    static constexpr int PKS = (2 * NORB + 3) / 4;
+    static constexpr int PNC = 3 * NORB;
+    static constexpr int PNT = (PNC + 15) / 16;
+    static constexpr int NPT = 2 * PMT * PNT;     // P tiles per chunk
     static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
-    static_assert(X_IPW <= 64 && P_IPW <= 64, "one item per lane");
+    static_assert(X_IPW <= 64, "one item per lane");
+    static_assert(NPT <= 32, "P tiles fit a 32-bit wave mask");
     static_assert(XP <= WAVES, "at most one extra (M-tile, N-tile) pair per wave");
 };
 
@@ -189,41 +196,74 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
         X[2 * x_item + 1] = acc.im;
     };
 
-    // ---- P chunk: P[(nl,i,j,re/im)][(el,c)] = sum_u X[el][nl][i][u] conj(gradH[n][j][c][u])
-    const int p_item = wave * C::P_IPW + lane;
-    const bool p_lane = lane < C::P_IPW && p_item < C::P_ITEMS;
-    const int p_i = p_item % 3, p_c = (p_item / 3) % NORB, p_nl = (p_item / (3 * NORB)) % 2,
-              p_el = p_item / (6 * NORB);
-    auto produce_p = [&](int64_t g) {
-        if (g >= niter || !p_lane) return;
-        const int ch = (int)(g % C::NCHUNK), np = ch % C::NP;
-        const int n = 2 * np + p_nl;
-        const double* X = sX + (g & 1) * C::XB + 2 * ((p_el * 2 + p_nl) * 3 + p_i) * NORB;
-        T* P = sP + (g & 1) * (C::KR * C::NCP) + p_el * NORB + p_c;
-        const int kr0 = (p_nl * 3 + p_i) * 3 * 2;
-        if (n < NB) {
-            cd xr[NORB];
-#pragma unroll
-            for (int u = 0; u < NORB; ++u) xr[u] = cd{X[2 * u], X[2 * u + 1]};
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const double* Ac = sA + 2 * ((n * 3 + j) * C::NN + p_c * NORB);
-                cd p{0.0, 0.0};
-#pragma unroll
-                for (int u = 0; u < NORB; ++u) cfma_conj(p, xr[u], cd{Ac[2 * u], Ac[2 * u + 1]});
-                P[(kr0 + 2 * j) * C::NCP] = T(p.re);
-                P[(kr0 + 2 * j + 1) * C::NCP] = T(p.im);
-            }
-        } else {
-#pragma unroll
-            for (int x = 0; x < 6; ++x) P[(kr0 + x) * C::NCP] = T(0);
-        }
-    };
-
     // ---- matrix-core work of this wave: its own M-tile against every N-tile, plus
     // at most one extra (M-tile, N-tile) pair from the M-tiles past the eighth
     const bool has_own = wave < C::OWN;
     const bool has_extra = wave < C::XP;
+
+    // ---- P tiles: P[(nl,i,j,re/im)][(el,c)] = sum_u X[el][nl][i][u] conj(gradH[n][j][c][u]),
+    // a small GEMM per neighbour of the chunk on the matrix cores.  Its tiles go to
+    // the waves whose SIMD carries the least GEMM work (same rule in every wave).
+    uint32_t my_tiles = 0;  // bit t set: P tile t belongs to this wave
+    {
+        int simd_load[4] = {0, 0, 0, 0};
+        for (int w = 0; w < C::WAVES; ++w)
+            simd_load[w % 4] += (w < C::OWN ? C::NT * C::KS : 0) + (w < C::XP ? C::KS : 0);
+        int wave_pt[C::WAVES];
+        for (int w = 0; w < C::WAVES; ++w) wave_pt[w] = 0;
+        for (int t = 0; t < C::NPT; ++t) {
+            int best = 0;
+            for (int w = 1; w < C::WAVES; ++w) {
+                const int lw = simd_load[w % 4], lb = simd_load[best % 4];
+                if (lw < lb || (lw == lb && wave_pt[w] < wave_pt[best])) best = w;
+            }
+            simd_load[best % 4] += C::PKS;
+            ++wave_pt[best];
+            if (best == wave) my_tiles |= 1u << t;
+        }
+    }
+    auto p_tiles = [&](int64_t g) {
+        if (g >= niter) return;
+        const int ch = (int)(g % C::NCHUNK), np = ch % C::NP;
+        const double* X = sX + (g & 1) * C::XB;
+        T* P = sP + (g & 1) * (C::KR * C::NCP);
+        for (uint32_t rest = my_tiles; rest != 0; rest &= rest - 1) {
+            const int t = __builtin_ctz(rest);
+            const int nt_p = t % C::PNT, mt_p = (t / C::PNT) % C::PMT, nl = t / (C::PNT * C::PMT);
+            const int n = 2 * np + nl;
+            // A operand (X embedding): row (el, i, re/im), column (u, re/im)
+            const int arow = 16 * mt_p + j16;
+            const int am = arow >> 1, arho = arow & 1, ael = am / 3, ai = am % 3;
+            const bool arow_ok = arow < C::PM_ROWS;
+            const bool aneg = arho == 0 && kap == 1;
+            const int abase = 2 * (((ael * 2 + nl) * 3 + ai) * NORB) + (arho ^ kap);
+            // B operand: conj(gradH[n][j][c][u]) parts, column (j, c)
+            const int bcol = 16 * nt_p + j16;
+            const int bj = bcol / NORB, bc = bcol % NORB;
+            const bool bcol_ok = bcol < C::PNC && n < NB;
+            const int bbase = 2 * ((n * 3 + bj) * C::NN + bc * NORB) + kap;
+            typename O::Acc acc{};
+#pragma unroll
+            for (int ks = 0; ks < C::PKS; ++ks) {
+                const int u = 2 * ks + (kk >> 1);  // K index 4ks+kk = (u, re/im)
+                const bool u_ok = u < NORB;
+                const double xa = X[(arow_ok && u_ok) ? abase + 2 * u : 0];
+                const double ab = sA[(bcol_ok && u_ok) ? bbase + 2 * u : 0];
+                const T av = (arow_ok && u_ok) ? O::neg_if(T(xa), aneg) : T(0);
+                const T bv = (bcol_ok && u_ok) ? T(kap ? -ab : ab) : T(0);
+                acc = O::mma(av, bv, acc);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * mt_p + O::row_of(lane, v);
+                if (row < C::PM_ROWS && bcol < C::PNC) {
+                    const int m = row >> 1, rho = row & 1, el = m / 3, i = m % 3;
+                    P[(((nl * 3 + i) * 3 + bj) * 2 + rho) * C::NCP + el * NORB + bc] = T(acc[v]);
+                }
+            }
+        }
+    };
+
     const int own_mt = wave;
     const int ext_mt = C::WAVES + (C::XP > 0 ? wave / C::NT : 0);
     const int ext_nt = C::XP > 0 ? wave % C::NT : 0;
@@ -353,21 +393,15 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     finish_x(0);
     __syncthreads();
     gather_g(1);
-    produce_p(0);
+    p_tiles(0);
     finish_x(1);
     __syncthreads();
 
     // ---- main loop: one barrier per chunk
-    const bool mfma_first = wave < 4;  // waves w and w+4 share a SIMD
     for (int64_t g = 0; g < niter; ++g) {
         gather_g(g + 2);  // G loads in flight under this chunk's matrix work
-        if (mfma_first) {
-            mfma_chunk(g);
-            produce_p(g + 1);
-        } else {
-            produce_p(g + 1);
-            mfma_chunk(g);
-        }
+        mfma_chunk(g);
+        p_tiles(g + 1);
         finish_x(g + 2);
         if ((g % C::NCHUNK) == C::NCHUNK - 1) {
             const int64_t blk = g / C::NCHUNK;

@@ -15,6 +15,12 @@ bool fwd_mfma_specialised(const Dims& d);
 hipError_t launch_fwd_mfma(const Dims& d, int precision, const double* G, const double* D, const double* A,
                            const int32_t* nbr, cd alpha, double* S, hipStream_t stream);
 
+// adjoint (fp64): reverse adjacency in the workspace, then dG/d gradH per neighbour atom and dD per edge
+size_t bwd_workspace_bytes(const Dims& d);
+bool bwd_supported(const Dims& d);
+hipError_t launch_bwd(const Dims& d, const double* G, const double* D, const double* A, const int32_t* nbr, cd alpha,
+                      const double* gS, double* dG, double* dD, double* dA, void* ws, hipStream_t stream);
+
 // neighbour-table range check: sets *flag (device int) to 1 if any entry is outside [0, na)
 hipError_t launch_check_nbr(const Dims& d, const int32_t* nbr, int* flag, hipStream_t stream);
 

@@ -1,0 +1,66 @@
+"""Parity at the device-scale workload (Na=4864, NE=1024, Nkz=Nqz=7, Nw=10,
+Nb=4, Norb=10; 55.8 GB of G) in the launch configuration the benchmark times,
+on sampled output blocks that the oracle computes one by one."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle
+from paper_1912_10024_amd import sse
+from paper_1912_10024_amd.inputs import CONFIGS, CONFIG_INDEX, Dims, generate_device
+
+pytestmark = pytest.mark.gpu
+
+
+def _compact(d, G, D, dH, nbr, atoms):
+    """Host copy of everything the outputs of `atoms` depend on, atoms renumbered."""
+    nbr_h = nbr.cpu().numpy()
+    keep = sorted(set(int(a) for a in atoms) | set(int(b) for a in atoms for b in nbr_h[a]))
+    remap = {a: i for i, a in enumerate(keep)}
+    idx = torch.tensor(keep, device=G.device)
+    sub = Dims(nkz=d.nkz, ne=d.ne, nqz=d.nqz, nw=d.nw, na=len(keep), nb=d.nb, norb=d.norb, g_slots=1)
+    Gs = np.ascontiguousarray(G[:, :, :, :1].index_select(2, idx).cpu().numpy())
+    Ds = np.ascontiguousarray(D.index_select(2, idx).cpu().numpy())
+    Hs = np.ascontiguousarray(dH.index_select(0, idx).cpu().numpy())
+    nb_s = np.zeros((len(keep), d.nb), dtype=np.int32)
+    aset = set(int(a) for a in atoms)
+    for a in keep:
+        nb_s[remap[a]] = [remap[int(b)] for b in nbr_h[a]] if a in aset else [(remap[a] + 1 + t) % len(keep) for t in range(d.nb)]
+    return sub, Gs, Ds, Hs, nb_s, remap
+
+
+@pytest.fixture(scope="module")
+def device_problem():
+    d = CONFIGS["device"]
+    print(f"[gpu] device-scale inputs {d.as_tuple()}", flush=True)
+    inp = generate_device(d, CONFIG_INDEX["device"], device="cuda")
+    sse.check_nbr(inp["nbr"], d.na)
+    yield d, inp
+    del inp
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
+def test_device_scale_sampled_parity(device_problem, precision, tol):
+    d, inp = device_problem
+    G, D, dH, nbr = inp["G<"], inp["D<"], inp["dH"], inp["nbr"]
+    print(f"[gpu] device-scale forward {precision}", flush=True)
+    S = sse.forward(G, D, dH, nbr, precision=precision)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(2024)
+    # first, last and random atoms; energy edges and interior; every kz
+    atoms = [0, d.na - 1] + [int(x) for x in rng.choice(d.na, size=2, replace=False)]
+    sub, Gs, Ds, Hs, nbs, remap = _compact(d, G, D, dH, nbr, atoms)
+    pts = []
+    for a in atoms:
+        for e in (0, 1, d.nw - 1, d.nw, d.ne // 2, d.ne - d.nw - 1, d.ne - 2, d.ne - 1):
+            pts.append((int(rng.integers(d.nkz)), e, a))
+        pts += [(int(rng.integers(d.nkz)), int(rng.integers(d.ne)), a) for _ in range(4)]
+    ref = oracle.sse_points(sub, Gs, Ds, Hs, nbs, [(k, e, remap[a]) for k, e, a in pts])
+    idx = torch.tensor(pts, device=G.device)
+    got = S[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy()
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    print(f"  {precision} device-scale sampled rel err {err:.3e} over {len(pts)} blocks", flush=True)
+    assert err <= tol
+    assert torch.isfinite(torch.view_as_real(S)).all()
+    del S
