@@ -160,7 +160,7 @@ def main():
     t_gen = time.perf_counter() - t_gen
 
     f_eff = flops.f_eff(d)
-    gemm = flops.pd_gemm_flops(d)
+    gemm = flops.pd_mfma_flops(d)
     peaks = {"fp64": FP64_MFMA_PEAK, "fp32": FP32_MFMA_PEAK, "bf16x3": BF16_MFMA_PEAK}
     outputs, res = {}, {}
     for form in forms:
@@ -176,7 +176,8 @@ def main():
             "kernel_ms_all": [round(x, 3) for x in kern_ms],
             "roofline": {"bound": "mfma", "achieved": round(achieved / 1e12, 3), "peak": peaks[form] / 1e12,
                          "unit": "TFLOP/s", "frac": round(achieved / peaks[form], 4), "traffic": None,
-                         "flops_per_launch": gemm, "what": f"dense P.D GEMM flops on {form} matrix cores"},
+                         "flops_per_launch": gemm,
+                         "what": f"useful {form} matrix-core flops: P.D GEMM + P = X.gradH^H products"},
         }
         outputs[form] = S
     head = forms[0]

@@ -38,7 +38,8 @@
  *     dSigma  like Sigma; dG like G; dD like D; ddH like dH
  * - Ownership: the caller allocates and frees every buffer, including the
  *   workspace (size from sse_workspace_bytes).  The library keeps no device
- *   allocations and does no host<->device copies, except sse_check_nbr.
+ *   allocations and does no host<->device copies, except the one status word
+ *   that sse_check_nbr and sse_combine_d read back.
  * - Calls are asynchronous on `stream` (a hipStream_t; NULL = the default
  *   stream).  Outputs are overwritten, never accumulated.  Inputs are only
  *   read.  Calls that use distinct outputs and workspaces may run
@@ -50,7 +51,7 @@
  *     limits, or an element count that overflows int64), SSE_ERR_WORKSPACE 3,
  *     SSE_ERR_PRECISION 4, SSE_ERR_HIP 5 (the message carries
  *     hipGetErrorString), SSE_ERR_NBR 6 (sse_check_nbr found an entry outside
- *     [0, na)).
+ *     [0, na), or sse_combine_d found the table not symmetric).
  *   sse_last_error() returns a thread-local description of the last failure.
  * - Kernels never read outside their inputs: a neighbour entry outside
  *   [0, na) contributes zero (validate tables with sse_check_nbr).
@@ -103,10 +104,11 @@ int sse_abi_version(void);
 const char* sse_last_error(void);
 
 /*
- * Bytes of workspace a call needs.  backward = 0 for sse_forward with the
- * given precision, 1 for sse_backward (precision ignored).  May be 0.
+ * Bytes of workspace a call needs.  op = 0 for sse_forward with the given
+ * precision, 1 for sse_backward, 2 for sse_combine_d (precision ignored for
+ * 1 and 2).
  */
-int sse_workspace_bytes(const sse_dims* dims, int precision, int backward, size_t* bytes);
+int sse_workspace_bytes(const sse_dims* dims, int precision, int op, size_t* bytes);
 
 /*
  * Effective flops of one sse_forward call (one component), the paper's
@@ -143,6 +145,21 @@ int sse_backward(const sse_dims* dims, const double* G, const double* D, const d
                  const int32_t* nbr, double alpha_re, double alpha_im, const double* dSigma,
                  double* dG, double* dD, double* ddH, void* workspace, size_t workspace_bytes,
                  void* stream);
+
+/*
+ * The bracket of Eq. 3 for every neighbour slot, the step that prepares D:
+ *   D[q,w,a,n,:,:] = Dfull[q,w,b,1+m] - Dfull[q,w,b,0] - Dfull[q,w,a,0] + Dfull[q,w,a,1+n]
+ * (= D_ba - D_bb - D_aa + D_ab) with b = nbr[a,n] and m the slot with
+ * nbr[b,m] = a.  Dfull [nqz][nw][na][nb+1][3][3] complex holds the phonon
+ * Green's function blocks the paper's SSE reads: slot 0 the diagonal block
+ * D_aa, slot 1+n the block coupling a to nbr[a,n].  Output D
+ * [nqz][nw][na][nb][3][3], the D argument of sse_forward.  The table must be
+ * symmetric (a in nbr[b] whenever b in nbr[a]); this is checked first,
+ * synchronously on `stream` (SSE_ERR_NBR, nothing written, if it fails).
+ * Workspace: sse_workspace_bytes(dims, 0, 2).
+ */
+int sse_combine_d(const sse_dims* dims, const double* Dfull, const int32_t* nbr, double* D, void* workspace,
+                  size_t workspace_bytes, void* stream);
 
 /*
  * Synchronous check of a neighbour table: returns SSE_OK if every entry lies

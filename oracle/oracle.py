@@ -40,7 +40,9 @@ def _open(path):
     lib.oracle_sse_forward.argtypes = [P, P, P, P, P, ctypes.c_double, ctypes.c_double, P]
     lib.oracle_sse_backward.argtypes = [P, P, P, P, P, ctypes.c_double, ctypes.c_double, P, P, P, P]
     lib.oracle_num_threads.argtypes = []
-    for f in (lib.oracle_sse_points, lib.oracle_sse_forward, lib.oracle_sse_backward, lib.oracle_num_threads):
+    lib.oracle_combine_d.argtypes = [P, P, P, P]
+    for f in (lib.oracle_sse_points, lib.oracle_sse_forward, lib.oracle_sse_backward, lib.oracle_num_threads,
+              lib.oracle_combine_d):
         f.restype = ctypes.c_int
     return lib
 
@@ -119,6 +121,19 @@ def sse_backward(dims, G, D, dH, nbr, dSigma, alpha=1j, need=("G", "D", "dH"), l
     return dG, dD, ddH
 
 
+def combine_d(dims, Dfull, nbr, lib=None) -> np.ndarray:
+    """The Eq. 3 bracket D_ba - D_bb - D_aa + D_ab per neighbour slot from the
+    [nqz, nw, na, nb+1, 3, 3] blocks (slot 0 = D_aa, slot 1+n = D_{a,nbr[a,n]})."""
+    _check(Dfull, (dims.nqz, dims.nw, dims.na, dims.nb + 1, 3, 3), np.complex128, "Dfull")
+    _check(nbr, dims.nbr_shape, np.int32, "nbr")
+    out = np.zeros(dims.d_shape, dtype=np.complex128)
+    dd = _dims_array(dims)
+    rc = (lib or _load()).oracle_combine_d(_ptr(dd), _ptr(Dfull), _ptr(nbr), _ptr(out))
+    if rc:
+        raise RuntimeError(f"oracle_combine_d failed with status {rc}")
+    return out
+
+
 def sse_status(dims_tuple, G, D, dH, nbr, lib=None) -> int:
     """Raw status of the forward entry point for arbitrary (possibly invalid) dims."""
     dd = np.asarray(dims_tuple, dtype=np.int64)
@@ -144,3 +159,6 @@ class Bound:
 
     def sse_status(self, *a, **k):
         return sse_status(*a, lib=self.lib, **k)
+
+    def combine_d(self, *a, **k):
+        return combine_d(*a, lib=self.lib, **k)

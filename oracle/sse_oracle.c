@@ -395,3 +395,39 @@ int oracle_sse_backward(const int64_t* dims, const double* G, const double* D, c
     }
     return fail ? 7 : 0;
 }
+
+/*
+ * The bracket of Eq. 3, D_ba - D_bb - D_aa + D_ab, for every pair (a, b = nbr[a,n]),
+ * from the phonon Green's function blocks of the paper's 6-D tensor
+ *   Dfull [nqz][nw][na][nb+1][3][3]: slot 0 = D_aa, slot 1+n = D_{a, nbr[a,n]}.
+ * D_ba is Dfull[.., b, 1+m] with nbr[b,m] = a (the table must be symmetric).
+ * Output Dc [nqz][nw][na][nb][3][3].  Returns 6 if some pair has no reverse slot.
+ */
+int oracle_combine_d(const int64_t* dims, const double* Dfull, const int32_t* nbr, double* Dc) {
+    odims d;
+    int rc = read_dims(dims, &d);
+    if (rc) return rc;
+    if (!Dfull || !nbr || !Dc) return 1;
+    if ((rc = check_nbr(&d, nbr))) return rc;
+    const int64_t S = d.nb + 1;
+    for (int64_t a = 0; a < d.na; ++a)
+        for (int64_t n = 0; n < d.nb; ++n) {
+            const int64_t b = nbr[a * d.nb + n];
+            int64_t m = -1;
+            for (int64_t t = 0; t < d.nb; ++t)
+                if (nbr[b * d.nb + t] == a) { m = t; break; }
+            if (m < 0) return 6;
+            for (int64_t q = 0; q < d.nqz; ++q)
+                for (int64_t w = 0; w < d.nw; ++w)
+                    for (int x = 0; x < 9; ++x) {
+                        const int64_t base = (q * d.nw + w) * d.na;
+                        const double* Dba = Dfull + 2 * (((base + b) * S + 1 + m) * 9 + x);
+                        const double* Dbb = Dfull + 2 * (((base + b) * S + 0) * 9 + x);
+                        const double* Daa = Dfull + 2 * (((base + a) * S + 0) * 9 + x);
+                        const double* Dab = Dfull + 2 * (((base + a) * S + 1 + n) * 9 + x);
+                        double* o = Dc + 2 * ((((base + a) * d.nb) + n) * 9 + x);
+                        for (int p = 0; p < 2; ++p) o[p] = ((Dba[p] - Dbb[p]) - Daa[p]) + Dab[p];
+                    }
+        }
+    return 0;
+}

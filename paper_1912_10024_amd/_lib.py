@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(HERE, "libsse.so")
 SSE_OK, SSE_ERR_NULL, SSE_ERR_DIMS, SSE_ERR_WORKSPACE, SSE_ERR_PRECISION, SSE_ERR_HIP, SSE_ERR_NBR = range(7)
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 3}
 EXPORTS = ("sse_abi_version", "sse_last_error", "sse_workspace_bytes", "sse_effective_flops",
-           "sse_forward", "sse_backward", "sse_check_nbr")
+           "sse_forward", "sse_backward", "sse_check_nbr", "sse_combine_d")
 
 
 class SSEDims(ctypes.Structure):
@@ -41,7 +41,9 @@ def load():
     lib.sse_forward.argtypes = [DP, P, P, P, P, D, D, ctypes.c_int, P, P, SZ, P]
     lib.sse_backward.argtypes = [DP, P, P, P, P, D, D, P, P, P, P, P, SZ, P]
     lib.sse_check_nbr.argtypes = [DP, P, P, SZ, P]
-    for f in (lib.sse_workspace_bytes, lib.sse_effective_flops, lib.sse_forward, lib.sse_backward, lib.sse_check_nbr):
+    lib.sse_combine_d.argtypes = [DP, P, P, P, P, SZ, P]
+    for f in (lib.sse_workspace_bytes, lib.sse_effective_flops, lib.sse_forward, lib.sse_backward, lib.sse_check_nbr,
+              lib.sse_combine_d):
         f.restype = ctypes.c_int
     _lib = lib
     return lib

@@ -73,11 +73,16 @@ int sse_workspace_bytes(const sse_dims* dims, int precision, int backward, size_
     int rc = check_dims(dims);
     if (rc) return rc;
     if (!bytes) return fail(SSE_ERR_NULL, "bytes is NULL");
-    if (!backward && precision != SSE_FP64 && precision != SSE_FP32 && precision != SSE_BF16X3)
+    if (backward == 0 && precision != SSE_FP64 && precision != SSE_FP32 && precision != SSE_BF16X3)
         return fail(SSE_ERR_PRECISION, "unknown precision %d", precision);
+    if (backward < 0 || backward > 2) return fail(SSE_ERR_DIMS, "op must be 0 (forward), 1 (backward) or 2 (combine_d)");
     size_t ws = 256;  // status flag of sse_check_nbr
-    if (backward) {
+    if (backward == 1) {
         const size_t b = sse::bwd_workspace_bytes(sse::to_dims(*dims));
+        if (b > ws) ws = b;
+    }
+    if (backward == 2) {
+        const size_t b = sse::combine_workspace_bytes(sse::to_dims(*dims));
         if (b > ws) ws = b;
     }
     *bytes = ws;
@@ -138,6 +143,30 @@ int sse_backward(const sse_dims* dims, const double* G, const double* D, const d
     hipError_t e = sse::launch_bwd(d, G, D, dH, nbr, sse::cd{alpha_re, alpha_im}, dSigma, dG, dD, ddH, workspace,
                                    reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "backward launch");
+    return ok();
+}
+
+int sse_combine_d(const sse_dims* dims, const double* Dfull, const int32_t* nbr, double* Dc, void* workspace,
+                  size_t workspace_bytes, void* stream) {
+    int rc = check_dims(dims);
+    if (rc) return rc;
+    if (!Dfull || !nbr || !Dc) return fail(SSE_ERR_NULL, "a tensor pointer is NULL");
+    if (!count_ok({dims->nqz, dims->nw, dims->na, dims->nb + 1, 9})) return fail(SSE_ERR_DIMS, "tensor sizes overflow int64");
+    const sse::Dims d = sse::to_dims(*dims);
+    const size_t need = sse::combine_workspace_bytes(d);
+    if (!workspace || workspace_bytes < need)
+        return fail(SSE_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace_bytes);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = sse::launch_reverse_slots(d, nbr, workspace, s);
+    if (e != hipSuccess) return hip_fail(e, "reverse-slot launch");
+    int host_flag = 0;
+    e = hipMemcpyAsync(&host_flag, workspace, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "reverse-slot copy");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "reverse-slot sync");
+    if (host_flag) return fail(SSE_ERR_NBR, "neighbour table is not symmetric or has an entry outside [0, na)");
+    e = sse::launch_combine_d(d, Dfull, nbr, Dc, workspace, s);
+    if (e != hipSuccess) return hip_fail(e, "combine_d launch");
     return ok();
 }
 

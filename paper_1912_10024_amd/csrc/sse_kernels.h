@@ -21,6 +21,12 @@ bool bwd_supported(const Dims& d);
 hipError_t launch_bwd(const Dims& d, const double* G, const double* D, const double* A, const int32_t* nbr, cd alpha,
                       const double* gS, double* dG, double* dD, double* dA, void* ws, hipStream_t stream);
 
+// Eq. 3 bracket from the full phonon blocks (symmetric neighbour table)
+size_t combine_workspace_bytes(const Dims& d);
+hipError_t launch_reverse_slots(const Dims& d, const int32_t* nbr, void* ws, hipStream_t stream);
+hipError_t launch_combine_d(const Dims& d, const double* Dfull, const int32_t* nbr, double* Dc, void* ws,
+                            hipStream_t stream);
+
 // neighbour-table range check: sets *flag (device int) to 1 if any entry is outside [0, na)
 hipError_t launch_check_nbr(const Dims& d, const int32_t* nbr, int* flag, hipStream_t stream);
 

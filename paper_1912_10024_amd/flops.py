@@ -46,6 +46,12 @@ def pd_left_flops(d) -> float:
     return 8.0 * d.norb ** 3 * 12 * d.nb * d.na * d.nkz * d.ne
 
 
+def pd_mfma_flops(d) -> float:
+    """Useful real flops the forward issues on the matrix cores: the P.D GEMM plus
+    the nine right products P_ij = X_i . grad_j H^H per (k', E', a, n)."""
+    return pd_gemm_flops(d) + 8.0 * d.norb ** 3 * 9 * d.nb * d.na * d.nkz * d.ne
+
+
 def pd_stencil_flops(d) -> float:
     """Real adds of the (w, +/-) energy stencil: 2 complex adds per valid (k, E, w, s, r, c)."""
     valid = 0

@@ -111,6 +111,28 @@ def make_nbr(rng: np.random.Generator, na: int, nb: int) -> np.ndarray:
     return nbr
 
 
+def make_symmetric_nbr(rng: np.random.Generator, na: int, nb: int) -> np.ndarray:
+    """A symmetric nb-regular table (nb even): atoms on a random permutation of a
+    ring, each linked to the nb/2 nearest ring positions on either side.  a is a
+    neighbour of b exactly when b is a neighbour of a, as for a real structure."""
+    if nb % 2 or nb > na - 1:
+        raise ValueError("need an even nb <= na - 1")
+    perm = rng.permutation(na)
+    pos = np.empty(na, dtype=np.int64)
+    pos[perm] = np.arange(na)
+    nbr = np.empty((na, nb), dtype=np.int32)
+    offs = [o for h in range(1, nb // 2 + 1) for o in (h, -h)]
+    for a in range(na):
+        nbr[a] = [perm[(pos[a] + o) % na] for o in offs]
+    return nbr
+
+
+def make_D_full(rng: np.random.Generator, dims: Dims) -> np.ndarray:
+    """Phonon Green's function blocks [nqz, nw, na, nb+1, 3, 3]: slot 0 is D_aa,
+    slot 1+n the block coupling a to its n-th neighbour; N(0,1) parts."""
+    return _cnormal(rng, (dims.nqz, dims.nw, dims.na, dims.nb + 1, N3D, N3D), 1.0)
+
+
 def anti_hermitian_blocks(x: np.ndarray) -> np.ndarray:
     """(X - X^H)/2 over the last two axes, in place."""
     xh = np.conj(np.swapaxes(x, -1, -2))

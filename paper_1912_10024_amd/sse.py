@@ -54,11 +54,13 @@ def _raise(rc: int, what: str):
         raise RuntimeError(f"{what} failed (status {rc}): {_lib.last_error()}")
 
 
-def workspace(d: Dims, precision: str = "fp64", backward: bool = False, device="cuda") -> torch.Tensor:
+def workspace(d: Dims, precision: str = "fp64", backward: bool = False, device="cuda", op: int = None) -> torch.Tensor:
+    """Workspace for sse_forward (op 0), sse_backward (op 1) or sse_combine_d (op 2)."""
     lib = _lib.load()
     nbytes = ctypes.c_size_t(0)
     cd = _lib.SSEDims.of(d)
-    _raise(lib.sse_workspace_bytes(ctypes.byref(cd), PRECISIONS.get(precision, -1), int(backward), ctypes.byref(nbytes)),
+    op = int(backward) if op is None else op
+    _raise(lib.sse_workspace_bytes(ctypes.byref(cd), PRECISIONS.get(precision, -1), op, ctypes.byref(nbytes)),
            "sse_workspace_bytes")
     return torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device=device)
 
@@ -79,6 +81,24 @@ def check_nbr(nbr: torch.Tensor, na: int) -> None:
     ws = workspace(d, device=nbr.device)
     cd = _lib.SSEDims.of(d)
     _raise(lib.sse_check_nbr(ctypes.byref(cd), _ptr(nbr), _ptr(ws), ws.numel(), _stream(nbr.device)), "sse_check_nbr")
+
+
+def combine_d(Dfull: torch.Tensor, nbr: torch.Tensor) -> torch.Tensor:
+    """Eq. 3 bracket D_ba - D_bb - D_aa + D_ab per neighbour slot from the
+    [nqz, nw, na, nb+1, 3, 3] phonon blocks; needs a symmetric neighbour table."""
+    _check_tensor(Dfull, "Dfull")
+    _check_tensor(nbr, "nbr", torch.int32)
+    if Dfull.dim() != 6 or Dfull.shape[4:] != (3, 3) or Dfull.shape[3] != nbr.shape[1] + 1 or Dfull.shape[2] != nbr.shape[0]:
+        raise ValueError(f"Dfull must be [nqz, nw, na, nb+1, 3, 3] for nbr {tuple(nbr.shape)}")
+    nqz, nw, na = Dfull.shape[:3]
+    d = Dims(nkz=nqz, ne=1, nqz=nqz, nw=nw, na=na, nb=nbr.shape[1], norb=1, g_slots=1)
+    out = torch.empty(d.d_shape, dtype=torch.complex128, device=Dfull.device)
+    ws = workspace(d, device=Dfull.device, op=2)
+    lib = _lib.load()
+    cd = _lib.SSEDims.of(d)
+    _raise(lib.sse_combine_d(ctypes.byref(cd), _ptr(Dfull), _ptr(nbr), _ptr(out), _ptr(ws), ws.numel(),
+                             _stream(Dfull.device)), "sse_combine_d")
+    return out
 
 
 def forward(G, D, dH, nbr, alpha=1j, precision: str = "fp64", out=None, ws=None) -> torch.Tensor:
