@@ -26,7 +26,6 @@ if ROOT not in sys.path:
 
 FP64_MFMA_PEAK = 78.6e12   # MI355X dense fp64 matrix peak, flop/s
 FP32_MFMA_PEAK = 157.3e12
-BF16_MFMA_PEAK = 2.5e15
 HBM_PEAK = 8.0e12
 
 
@@ -161,7 +160,7 @@ def main():
 
     f_eff = flops.f_eff(d)
     gemm = flops.pd_mfma_flops(d)
-    peaks = {"fp64": FP64_MFMA_PEAK, "fp32": FP32_MFMA_PEAK, "bf16x3": BF16_MFMA_PEAK}
+    peaks = {"fp64": FP64_MFMA_PEAK, "fp32": FP32_MFMA_PEAK}
     outputs, res = {}, {}
     for form in forms:
         S = torch.empty(d.sigma_shape, dtype=torch.complex128, device=dev)

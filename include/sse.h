@@ -80,11 +80,10 @@ typedef struct sse_dims {
 } sse_dims;
 
 enum sse_precision {
-    SSE_FP64 = 0,    /* fp64 products on matrix cores, fp64 reduction           */
-    SSE_FP32 = 1,    /* products in fp32 (fp32 matrix cores), fp64 reduction    */
-    SSE_BF16X3 = 3   /* each fp32 operand split in three bf16 terms; the six
-                        products above 2^-24 on bf16 matrix cores with fp32
-                        accumulation; fp64 reduction                            */
+    SSE_FP64 = 0,    /* fp64 products on matrix cores, fp64 reduction                  */
+    SSE_FP32 = 1     /* operands of the dense products rounded to fp32 after the fp64
+                        gather, fp32 matrix cores, each 36-term K chunk accumulated in
+                        fp32 then added in fp64; fp64 (qz, w, +/-) reduction            */
 };
 
 enum sse_status {
