@@ -109,6 +109,22 @@ def cpu_baseline(d, G, D, dH, nbr, outputs, target_s, f_block, seed=7):
     }, errs
 
 
+def recorded_traffic():
+    """HBM bytes per launch of the fp64 kernel from the committed rocprofv3
+    counters, if the kernel source is unchanged since they were taken."""
+    import hashlib
+
+    rec = os.path.join(ROOT, "profiles", "fwd_mfma_device_traffic.txt")
+    src = os.path.join(ROOT, "paper_1912_10024_amd", "csrc", "fwd_mfma.hip")
+    if not os.path.exists(rec):
+        return None
+    kv = dict(l.strip().split("=", 1) for l in open(rec) if "=" in l and not l.startswith("#"))
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if kv.get("kernel_source_sha256") != sha:
+        return None
+    return float(kv["fetch_bytes"]) + float(kv["write_bytes"])
+
+
 def time_form(sse, G, D, dH, nbr, S, ws, form, steps, warmup, dev):
     import torch
 
@@ -180,6 +196,8 @@ def main():
         }
         outputs[form] = S
     head = forms[0]
+    if head == "fp64" and args.config == "device":
+        res[head]["roofline"]["traffic"] = recorded_traffic()
     line = {
         "metric": "SSE effective TFLOP/s (paper's regrouped flop count, one Sigma component), fp64 vs mixed",
         "value": round(res[head]["value"], 3),
