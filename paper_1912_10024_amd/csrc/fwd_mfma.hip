@@ -89,7 +89,10 @@ struct Fwd64 {
     // LDS carve-up: D table and P chunks in the operand type, the rest in doubles
     static constexpr int L_D = ZOFF + NP * 36 + 4;
     static constexpr int L_A = NB * 3 * NN * 2;
-    static constexpr int L_P = 2 * KR * NCP;
+    // two P buffers; the slot after each takes the padding results of the P tiles
+    static constexpr int PBS = KR * NCP + 2;
+    static constexpr int TRASH = KR * NCP;
+    static constexpr int L_P = 2 * PBS;
     static constexpr int XB = EB * 2 * 3 * NORB * 2;  // one X buffer: [el][nl][i][u] complex
     static constexpr int L_X = 2 * XB;
     static constexpr int RP = NKZ * NORB * 2;  // one ring plane: [k][c] complex
@@ -112,6 +115,33 @@ struct Fwd64 {
     static_assert(XP <= WAVES, "at most one extra (M-tile, N-tile) pair per wave");
 };
 
+// Static deal of the P tiles of a chunk to waves: each tile goes to a wave on
+// the SIMD with the least matrix work so far (the two waves of SIMD s are s
+// and s + 4), ties to the wave with fewer tiles.
+template <class C>
+struct PTileDeal {
+    uint32_t mask[C::WAVES];
+    int count[C::WAVES];
+    int maxper;
+    constexpr PTileDeal() : mask{}, count{}, maxper(0) {
+        int simd_load[4] = {0, 0, 0, 0};
+        for (int w = 0; w < C::WAVES; ++w)
+            simd_load[w % 4] += (w < C::OWN ? C::NT * C::KS : 0) + (w < C::XP ? C::KS : 0);
+        for (int t = 0; t < C::NPT; ++t) {
+            int best = 0;
+            for (int w = 1; w < C::WAVES; ++w) {
+                const int lw = simd_load[w % 4], lb = simd_load[best % 4];
+                if (lw < lb || (lw == lb && count[w] < count[best])) best = w;
+            }
+            simd_load[best % 4] += C::PKS;
+            mask[best] |= 1u << t;
+            ++count[best];
+        }
+        for (int w = 0; w < C::WAVES; ++w)
+            if (count[w] > maxper) maxper = count[w];
+    }
+};
+
 template <int NORB, int NKZ, int NW, int NB, int EB, int PREC>
 __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __restrict__ G,
                                                        const double* __restrict__ Dg,
@@ -121,6 +151,8 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     using C = Fwd64<NORB, NKZ, NW, NB, EB, PREC>;
     using O = Oper<PREC>;
     using T = typename O::T;
+    constexpr PTileDeal<C> deal{};
+    constexpr int MAXT = deal.maxper;
     extern __shared__ double lds[];
     T* sD = reinterpret_cast<T*>(lds);
     T* sP = sD + C::L_D;
@@ -154,9 +186,10 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     for (int x = tid; x < C::L_P; x += C::THREADS) sP[x] = T(0);
     for (int x = tid; x < C::L_R; x += C::THREADS) sR[x] = 0.0;
 
-    const int64_t NE = d.ne;
-    const int64_t nblk = (NE + EB - 1) / EB;
-    const int64_t niter = nblk * C::NCHUNK;
+    // chunk and energy indices fit 32 bits: the dispatcher admits ne < 2^28
+    const int NE = (int)d.ne;
+    const int nblk = (NE + EB - 1) / EB;
+    const int niter = nblk * C::NCHUNK;
     const int kk = lane >> 4, kap = kk & 1, j16 = lane & 15;
 
     // ---- X rows, step 1: gather this lane's G column for chunk g into registers
@@ -164,106 +197,117 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     const bool x_lane = lane < C::X_IPW && x_item < C::X_ITEMS;
     const int x_u = x_item % NORB, x_i = (x_item / NORB) % 3, x_nl = (x_item / (3 * NORB)) % 2,
               x_el = x_item / (6 * NORB);
-    cd gv[NORB];
-    auto gather_g = [&](int64_t g) {
+    // neighbour atom of this lane's slot in each pair, -1 if the slot is padding
+    // or the table entry lies outside [0, na) (such a neighbour contributes zero)
+    const int64_t na = d.na, g_stride = d.gs * C::NN;
+    int32_t nb_of[C::NP];
 #pragma unroll
-        for (int t = 0; t < NORB; ++t) gv[t] = cd{0.0, 0.0};
-        if (g >= niter || !x_lane) return;
-        const int64_t blk = g / C::NCHUNK;
-        const int ch = (int)(g % C::NCHUNK), kp = ch / C::NP, np = ch % C::NP;
-        const int n = 2 * np + x_nl;
-        const int64_t e = blk * EB + x_el;
-        if (n >= NB || e >= NE) return;
-        const int32_t b = nbr[a * NB + n];
-        if (b < 0 || b >= d.na) return;  // out-of-range neighbour contributes zero
-        const double* Gb = G + 2 * off_G(d, kp, e, b);
+    for (int p = 0; p < C::NP; ++p) {
+        const int n = 2 * p + x_nl;
+        const int32_t b = n < NB ? nbr[a * NB + n] : -1;
+        nb_of[p] = (b >= 0 && b < na) ? b : -1;
+    }
+    // Branch-free gather: an invalid lane loads from the start of G (in bounds)
+    // and finish_x writes zero for it.
+    cd gv[NORB];
+    bool g_ok = false;
+    auto gather_g = [&](int g) {
+        const int gg = g < niter ? g : 0;
+        const int blk = gg / C::NCHUNK;
+        const int ch = gg % C::NCHUNK, kp = ch / C::NP, np = ch % C::NP;
+        int32_t b = nb_of[0];
+#pragma unroll
+        for (int p = 1; p < C::NP; ++p) b = np == p ? nb_of[p] : b;
+        const int e = blk * EB + x_el;
+        g_ok = g < niter && x_lane && b >= 0 && e < NE;
+        const int64_t off = g_ok ? (((int64_t)kp * NE + e) * na + b) * g_stride : 0;
+        const double* Gb = G + 2 * off;
 #pragma unroll
         for (int t = 0; t < NORB; ++t) gv[t] = cload(Gb, t * NORB + x_u);
     };
     // ---- X rows, step 2: X[el][nl][i][u] = sum_t gradH[n][i][r][t] G[t][u]
-    auto finish_x = [&](int64_t g) {
+    auto finish_x = [&](int g) {
         if (g >= niter || !x_lane) return;
-        const int ch = (int)(g % C::NCHUNK), np = ch % C::NP;
-        const int n = 2 * np + x_nl;
+        const int ch = g % C::NCHUNK, np = ch % C::NP;
+        const int n = 2 * np + x_nl < NB ? 2 * np + x_nl : 0;
+        const double* Ar = sA + 2 * ((n * 3 + x_i) * C::NN + r * NORB);
         cd acc{0.0, 0.0};
-        if (n < NB) {
-            const double* Ar = sA + 2 * ((n * 3 + x_i) * C::NN + r * NORB);
 #pragma unroll
-            for (int t = 0; t < NORB; ++t) cfma(acc, cd{Ar[2 * t], Ar[2 * t + 1]}, gv[t]);
-        }
+        for (int t = 0; t < NORB; ++t) cfma(acc, cd{Ar[2 * t], Ar[2 * t + 1]}, gv[t]);
         double* X = sX + (g & 1) * C::XB;
-        X[2 * x_item] = acc.re;
-        X[2 * x_item + 1] = acc.im;
+        X[2 * x_item] = g_ok ? acc.re : 0.0;
+        X[2 * x_item + 1] = g_ok ? acc.im : 0.0;
+    };
+
+    // ---- P tiles of this wave: per-lane operand and output offsets, fixed for the
+    // whole sweep (only the X/P buffer parity and the neighbour pair change)
+    const uint32_t my_tiles = deal.mask[wave];
+    const int my_count = deal.count[wave];
+    int pt_a[MAXT > 0 ? MAXT : 1];       // X-embedding offset (doubles), -1: zero operand
+    int pt_b[MAXT > 0 ? MAXT : 1];       // conj(grad H) offset for the first pair, -1: zero
+    int pt_nl[MAXT > 0 ? MAXT : 1];
+    int pt_out[MAXT > 0 ? MAXT : 1][4];  // P offsets of the four results (padding: the spare slot)
+    bool pt_neg[MAXT > 0 ? MAXT : 1];
+    {
+        uint32_t rest = my_tiles;
+#pragma unroll
+        for (int si = 0; si < MAXT; ++si) {
+            const int t = rest ? __builtin_ctz(rest) : 0;
+            rest &= rest - 1;
+            const int nt_p = t % C::PNT, mt_p = (t / C::PNT) % C::PMT, nl = t / (C::PNT * C::PMT);
+            const int arow = 16 * mt_p + j16;
+            const int am = arow >> 1, arho = arow & 1, ael = am / 3, ai = am % 3;
+            pt_a[si] = arow < C::PM_ROWS ? 2 * (((ael * 2 + nl) * 3 + ai) * NORB) + (arho ^ kap) : -1;
+            pt_neg[si] = arho == 0 && kap == 1;
+            const int bcol = 16 * nt_p + j16;
+            const int bj = bcol / NORB, bc = bcol % NORB;
+            pt_b[si] = bcol < C::PNC ? 2 * ((nl * 3 + bj) * C::NN + bc * NORB) + kap : -1;
+            pt_nl[si] = nl;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * mt_p + O::row_of(lane, v);
+                const int m = row >> 1, rho = row & 1, el = m / 3, i = m % 3;
+                pt_out[si][v] = (row < C::PM_ROWS && bcol < C::PNC)
+                                    ? (((nl * 3 + i) * 3 + bj) * 2 + rho) * C::NCP + el * NORB + bc
+                                    : C::TRASH;
+
+            }
+        }
+    }
+    auto p_tiles = [&](int g) {
+        if (g >= niter) return;
+        const int np = (g % C::NCHUNK) % C::NP;
+        const double* X = sX + (g & 1) * C::XB;
+        T* P = sP + (g & 1) * C::PBS;
+#pragma unroll
+        for (int si = 0; si < MAXT; ++si) {
+            if (si < my_count) {
+                const bool n_ok = 2 * np + pt_nl[si] < NB;
+                const bool a_ok = pt_a[si] >= 0, b_ok = pt_b[si] >= 0 && n_ok;
+                const double* xa = X + (a_ok ? pt_a[si] : 0);
+                const double* ab = sA + (b_ok ? pt_b[si] + np * (2 * 3 * C::NN * 2) : 0);
+                typename O::Acc acc{};
+#pragma unroll
+                for (int ks = 0; ks < C::PKS; ++ks) {
+                    const int u = 2 * ks + (kk >> 1);  // K index 4ks+kk = (u, re/im)
+                    const bool u_ok = u < NORB;
+                    const double xv = xa[u_ok ? 2 * u : 0];
+                    const double bvv = ab[u_ok ? 2 * u : 0];
+                    const T av = (a_ok && u_ok) ? O::neg_if(T(xv), pt_neg[si]) : T(0);
+                    const T bv = (b_ok && u_ok) ? T(kap ? -bvv : bvv) : T(0);
+                    acc = O::mma(av, bv, acc);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    P[pt_out[si][v]] = T(acc[v]);
+            }
+        }
     };
 
     // ---- matrix-core work of this wave: its own M-tile against every N-tile, plus
     // at most one extra (M-tile, N-tile) pair from the M-tiles past the eighth
-    const bool has_own = wave < C::OWN;
+    const bool has_own = (C::OWN == C::WAVES) || wave < C::OWN;
     const bool has_extra = wave < C::XP;
-
-    // ---- P tiles: P[(nl,i,j,re/im)][(el,c)] = sum_u X[el][nl][i][u] conj(gradH[n][j][c][u]),
-    // a small GEMM per neighbour of the chunk on the matrix cores.  Its tiles go to
-    // the waves whose SIMD carries the least GEMM work (same rule in every wave).
-    uint32_t my_tiles = 0;  // bit t set: P tile t belongs to this wave
-    {
-        int simd_load[4] = {0, 0, 0, 0};
-        for (int w = 0; w < C::WAVES; ++w)
-            simd_load[w % 4] += (w < C::OWN ? C::NT * C::KS : 0) + (w < C::XP ? C::KS : 0);
-        int wave_pt[C::WAVES];
-        for (int w = 0; w < C::WAVES; ++w) wave_pt[w] = 0;
-        for (int t = 0; t < C::NPT; ++t) {
-            int best = 0;
-            for (int w = 1; w < C::WAVES; ++w) {
-                const int lw = simd_load[w % 4], lb = simd_load[best % 4];
-                if (lw < lb || (lw == lb && wave_pt[w] < wave_pt[best])) best = w;
-            }
-            simd_load[best % 4] += C::PKS;
-            ++wave_pt[best];
-            if (best == wave) my_tiles |= 1u << t;
-        }
-    }
-    auto p_tiles = [&](int64_t g) {
-        if (g >= niter) return;
-        const int ch = (int)(g % C::NCHUNK), np = ch % C::NP;
-        const double* X = sX + (g & 1) * C::XB;
-        T* P = sP + (g & 1) * (C::KR * C::NCP);
-        for (uint32_t rest = my_tiles; rest != 0; rest &= rest - 1) {
-            const int t = __builtin_ctz(rest);
-            const int nt_p = t % C::PNT, mt_p = (t / C::PNT) % C::PMT, nl = t / (C::PNT * C::PMT);
-            const int n = 2 * np + nl;
-            // A operand (X embedding): row (el, i, re/im), column (u, re/im)
-            const int arow = 16 * mt_p + j16;
-            const int am = arow >> 1, arho = arow & 1, ael = am / 3, ai = am % 3;
-            const bool arow_ok = arow < C::PM_ROWS;
-            const bool aneg = arho == 0 && kap == 1;
-            const int abase = 2 * (((ael * 2 + nl) * 3 + ai) * NORB) + (arho ^ kap);
-            // B operand: conj(gradH[n][j][c][u]) parts, column (j, c)
-            const int bcol = 16 * nt_p + j16;
-            const int bj = bcol / NORB, bc = bcol % NORB;
-            const bool bcol_ok = bcol < C::PNC && n < NB;
-            const int bbase = 2 * ((n * 3 + bj) * C::NN + bc * NORB) + kap;
-            typename O::Acc acc{};
-#pragma unroll
-            for (int ks = 0; ks < C::PKS; ++ks) {
-                const int u = 2 * ks + (kk >> 1);  // K index 4ks+kk = (u, re/im)
-                const bool u_ok = u < NORB;
-                const double xa = X[(arow_ok && u_ok) ? abase + 2 * u : 0];
-                const double ab = sA[(bcol_ok && u_ok) ? bbase + 2 * u : 0];
-                const T av = (arow_ok && u_ok) ? O::neg_if(T(xa), aneg) : T(0);
-                const T bv = (bcol_ok && u_ok) ? T(kap ? -ab : ab) : T(0);
-                acc = O::mma(av, bv, acc);
-            }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = 16 * mt_p + O::row_of(lane, v);
-                if (row < C::PM_ROWS && bcol < C::PNC) {
-                    const int m = row >> 1, rho = row & 1, el = m / 3, i = m % 3;
-                    P[(((nl * 3 + i) * 3 + bj) * 2 + rho) * C::NCP + el * NORB + bc] = T(acc[v]);
-                }
-            }
-        }
-    };
-
     const int own_mt = wave;
     const int ext_mt = C::WAVES + (C::XP > 0 ? wave / C::NT : 0);
     const int ext_nt = C::XP > 0 ? wave % C::NT : 0;
@@ -277,69 +321,78 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
         base = (pad ? 0 : (kw % NW) * C::WS) + (rho ^ kap) - kap + kk;
     };
     int own_k, own_base, ext_k, ext_base;
-    bool own_neg, ext_neg;
-    bool own_pad, ext_pad;
+    bool own_neg, ext_neg, own_pad, ext_pad;
     row_info(own_mt, own_k, own_base, own_neg, own_pad);
     row_info(ext_mt, ext_k, ext_base, ext_neg, ext_pad);
 
     // fp64 accumulators of the energy block (for fp32 operands the matrix cores
     // accumulate one K chunk in fp32, which is then added here)
     f64x4 acc[C::NT];
-    f64x4 acc_x = f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int nt = 0; nt < C::NT; ++nt) acc[nt] = f64x4{0.0, 0.0, 0.0, 0.0};
-
+    f64x4 acc_x;
     auto a_ptr = [&](int k, int base, bool pad, int kp, int np) -> const T* {
         const int q = (k - kp + NKZ) % NKZ;
         return sD + (pad ? C::ZOFF : q * C::QS) + base + np * 36;
     };
-    auto mfma_chunk = [&](int64_t g) {
-        const int ch = (int)(g % C::NCHUNK), kp = ch / C::NP, np = ch % C::NP;
-        const T* Pb = sP + (g & 1) * (C::KR * C::NCP) + kk * C::NCP + j16;
-        if (has_own) {
-            const T* Ab = a_ptr(own_k, own_base, own_pad, kp, np);
+    // The A operands of the chunk are loaded up front and the B operands one
+    // k-step ahead, so LDS latency hides under the matrix instructions.
+    auto mfma_chunk = [&](int g) {
+        const int ch = g % C::NCHUNK, kp = ch / C::NP, np = ch % C::NP;
+        const T* Pb = sP + (g & 1) * C::PBS + kk * C::NCP + j16;
+        const T* Ao = a_ptr(own_k, own_base, own_pad, kp, np);
+        const T* Ax = a_ptr(ext_k, ext_base, ext_pad, kp, np);
+        const T* Px = Pb + 16 * ext_nt;
+        T ao[C::KS], ax[C::KS];
+#pragma unroll
+        for (int ks = 0; ks < C::KS; ++ks) {
+            // rows of a wave without such a tile are padding rows: they read zeros
+            ao[ks] = Ao[4 * ks];
+            ax[ks] = Ax[4 * ks];
+        }
+        T bv[2][C::NT], bx[2];
+#pragma unroll
+        for (int nt = 0; nt < C::NT; ++nt) bv[0][nt] = Pb[16 * nt];
+        bx[0] = Px[0];
+        typename O::Acc part[C::NT], part_x;
+        if constexpr (PREC != SSE_FP64) {
+#pragma unroll
+            for (int nt = 0; nt < C::NT; ++nt) part[nt] = typename O::Acc{0, 0, 0, 0};
+            part_x = typename O::Acc{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int ks = 0; ks < C::KS; ++ks) {
+            const int cur = ks & 1, nxt = cur ^ 1;
+            if (ks + 1 < C::KS) {
+#pragma unroll
+                for (int nt = 0; nt < C::NT; ++nt) bv[nxt][nt] = Pb[4 * (ks + 1) * C::NCP + 16 * nt];
+                bx[nxt] = Px[4 * (ks + 1) * C::NCP];
+            }
+            const T a = O::neg_if(ao[ks], own_neg), b = O::neg_if(ax[ks], ext_neg);
             if constexpr (PREC == SSE_FP64) {
+                if (has_own) {
 #pragma unroll
-                for (int ks = 0; ks < C::KS; ++ks) {
-                    const T av = O::neg_if(Ab[4 * ks], own_neg);
-#pragma unroll
-                    for (int nt = 0; nt < C::NT; ++nt) acc[nt] = O::mma(av, Pb[4 * ks * C::NCP + 16 * nt], acc[nt]);
+                    for (int nt = 0; nt < C::NT; ++nt) acc[nt] = O::mma(a, bv[cur][nt], acc[nt]);
                 }
+                if (has_extra) acc_x = O::mma(b, bx[cur], acc_x);
             } else {
-                typename O::Acc part[C::NT];
+                if (has_own) {
 #pragma unroll
-                for (int nt = 0; nt < C::NT; ++nt) part[nt] = typename O::Acc{0, 0, 0, 0};
-#pragma unroll
-                for (int ks = 0; ks < C::KS; ++ks) {
-                    const T av = O::neg_if(Ab[4 * ks], own_neg);
-#pragma unroll
-                    for (int nt = 0; nt < C::NT; ++nt) part[nt] = O::mma(av, Pb[4 * ks * C::NCP + 16 * nt], part[nt]);
+                    for (int nt = 0; nt < C::NT; ++nt) part[nt] = O::mma(a, bv[cur][nt], part[nt]);
                 }
-#pragma unroll
-                for (int nt = 0; nt < C::NT; ++nt)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) acc[nt][v] += (double)part[nt][v];
+                if (has_extra) part_x = O::mma(b, bx[cur], part_x);
             }
         }
-        if (has_extra) {
-            const T* Ab = a_ptr(ext_k, ext_base, ext_pad, kp, np);
-            if constexpr (PREC == SSE_FP64) {
+        if constexpr (PREC != SSE_FP64) {
 #pragma unroll
-                for (int ks = 0; ks < C::KS; ++ks)
-                    acc_x = O::mma(O::neg_if(Ab[4 * ks], ext_neg), Pb[4 * ks * C::NCP + 16 * ext_nt], acc_x);
-            } else {
-                typename O::Acc part{0, 0, 0, 0};
+            for (int nt = 0; nt < C::NT; ++nt)
 #pragma unroll
-                for (int ks = 0; ks < C::KS; ++ks)
-                    part = O::mma(O::neg_if(Ab[4 * ks], ext_neg), Pb[4 * ks * C::NCP + 16 * ext_nt], part);
+                for (int v = 0; v < 4; ++v) acc[nt][v] += (double)part[nt][v];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) acc_x[v] += (double)part[v];
-            }
+            for (int v = 0; v < 4; ++v) acc_x[v] += (double)part_x[v];
         }
     };
 
     // ---- add one V tile of energy block blk into the output ring
-    auto scatter_tile = [&](int64_t blk, int mt, int nt, const f64x4& v4) {
+    auto scatter_tile = [&](int blk, int mt, int nt, const f64x4& v4) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = 16 * mt + O::row_of(lane, v);
@@ -347,45 +400,46 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
             if (row < C::MROWS && col < C::NCOLS) {
                 const int rho = row & 1, kw = row >> 1, k = kw / NW, w = kw % NW + 1;
                 const int el = col / NORB, c = col % NORB;
-                const int64_t es = blk * EB + el;
+                const int es = blk * EB + el;
                 if (es < NE) {
-                    const int64_t lo = es - w, hi = es + w;
+                    const int lo = es - w, hi = es + w;
                     const int off = (k * NORB + c) * 2 + rho;
-                    if (lo >= 0) atomicAdd(&sR[(int)(lo % C::RING) * C::RP + off], v4[v]);
-                    if (hi < NE) atomicAdd(&sR[(int)(hi % C::RING) * C::RP + off], v4[v]);
+                    if (lo >= 0) atomicAdd(&sR[(lo % C::RING) * C::RP + off], v4[v]);
+                    if (hi < NE) atomicAdd(&sR[(hi % C::RING) * C::RP + off], v4[v]);
                 }
             }
         }
     };
-    auto scatter = [&](int64_t blk) {
+    auto scatter = [&](int blk) {
         if (has_own) {
 #pragma unroll
-            for (int nt = 0; nt < C::NT; ++nt) {
-                scatter_tile(blk, own_mt, nt, acc[nt]);
-                acc[nt] = f64x4{0.0, 0.0, 0.0, 0.0};
-            }
+            for (int nt = 0; nt < C::NT; ++nt) scatter_tile(blk, own_mt, nt, acc[nt]);
         }
-        if (has_extra) {
-            scatter_tile(blk, ext_mt, ext_nt, acc_x);
-            acc_x = f64x4{0.0, 0.0, 0.0, 0.0};
-        }
+        if (has_extra) scatter_tile(blk, ext_mt, ext_nt, acc_x);
     };
 
     // ---- scale by alpha and store output planes [e_lo, e_hi); clear their ring slots
-    auto write_planes = [&](int64_t e_lo, int64_t e_hi) {
+    auto write_planes = [&](int e_lo, int e_hi) {
         if (e_lo < 0) e_lo = 0;
         if (e_hi > NE) e_hi = NE;
         const int per = NKZ * NORB;
-        for (int64_t x = tid; x < (e_hi - e_lo) * per; x += C::THREADS) {
-            const int64_t e = e_lo + x / per;
-            const int kc = (int)(x % per), k = kc / NORB, c = kc % NORB;
-            double* slot = sR + (int)(e % C::RING) * C::RP + kc * 2;
+        for (int x = tid; x < (e_hi - e_lo) * per; x += C::THREADS) {
+            const int e = e_lo + x / per;
+            const int kc = x % per, k = kc / NORB, c = kc % NORB;
+            double* slot = sR + (e % C::RING) * C::RP + kc * 2;
             const cd v{slot[0], slot[1]};
             slot[0] = 0.0;
             slot[1] = 0.0;
-            cstore(S, off_S(d, k, e, a) + r * NORB + c, cmul(alpha, v));
+            cstore(S, (((int64_t)k * NE + e) * na + a) * C::NN + r * NORB + c, cmul(alpha, v));
         }
     };
+
+    // ---- the two waves of a SIMD (w and w+4) run opposite phases: waves 0-3
+    // issue their matrix work first and form P and X afterwards, waves 4-7 form
+    // P and X (from G loads issued in the previous chunk) first, so the vector
+    // work of one wave runs under the matrix work of the other.  Every phase has
+    // one call site, which keeps the accumulators in place across the loop.
+    const bool mfma_first = wave < 4;
 
     // ---- prologue: X for chunks 0 and 1, P for chunk 0
     __syncthreads();
@@ -395,24 +449,34 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     gather_g(1);
     p_tiles(0);
     finish_x(1);
+    if (!mfma_first) gather_g(2);
     __syncthreads();
 
-    // ---- main loop: one barrier per chunk
-    for (int64_t g = 0; g < niter; ++g) {
-        gather_g(g + 2);  // G loads in flight under this chunk's matrix work
-        mfma_chunk(g);
-        p_tiles(g + 1);
-        finish_x(g + 2);
-        if ((g % C::NCHUNK) == C::NCHUNK - 1) {
-            const int64_t blk = g / C::NCHUNK;
-            // fixed wave order keeps the fp64 sums bitwise reproducible
-            for (int w = 0; w < C::WAVES; ++w) {
-                if (wave == w) scatter(blk);
-                __syncthreads();
+    // ---- main loop: energy blocks, K chunks inside, one barrier per chunk
+    for (int blk = 0; blk < nblk; ++blk) {
+#pragma unroll
+        for (int nt = 0; nt < C::NT; ++nt) acc[nt] = f64x4{0.0, 0.0, 0.0, 0.0};
+        acc_x = f64x4{0.0, 0.0, 0.0, 0.0};
+        for (int ch = 0; ch < C::NCHUNK; ++ch) {
+            const int g = blk * C::NCHUNK + ch;
+            if (!mfma_first) {
+                finish_x(g + 2);  // G for chunk g+2 was gathered during chunk g-1
+                p_tiles(g + 1);
             }
-            write_planes(blk * EB - NW, (blk + 1) * EB - NW);
+            gather_g(mfma_first ? g + 2 : g + 3);  // loads in flight under the matrix work
+            mfma_chunk(g);
+            if (mfma_first) {
+                p_tiles(g + 1);
+                finish_x(g + 2);
+            }
+            __syncthreads();
         }
-        __syncthreads();
+        // fixed wave order keeps the fp64 sums bitwise reproducible
+        for (int w = 0; w < C::WAVES; ++w) {
+            if (wave == w) scatter(blk);
+            __syncthreads();
+        }
+        write_planes(blk * EB - NW, (blk + 1) * EB - NW);
     }
     write_planes(nblk * EB - NW, NE);
 }
@@ -435,6 +499,7 @@ static hipError_t launch_fwd(const Dims& d, const double* G, const double* D, co
 }
 
 bool fwd_mfma_specialised(const Dims& d) {
+    if (d.ne >= (int64_t(1) << 28)) return false;  // 32-bit chunk indices
     return (d.norb == 10 && d.nkz == 7 && d.nw == 10 && d.nb == 4) || (d.norb == 4 && d.nkz == 3 && d.nw == 2 && d.nb == 4) ||
            (d.norb == 10 && d.nkz == 7 && d.nw == 10 && d.nb == 3);
 }
