@@ -82,6 +82,7 @@ struct Fwd64 {
     static constexpr int QS = NW * WS;
     static constexpr int ZOFF = NKZ * QS;        // zero region read by padding rows
     static constexpr int NN = NORB * NORB;
+    static constexpr int NWV = NW;
     // wave -> M-tile ownership: waves own whole M-tiles (all N-tiles); the
     // M-tiles past the eighth are dealt out one (M-tile, N-tile) pair per wave
     static constexpr int OWN = MT < WAVES ? MT : WAVES;
@@ -113,6 +114,7 @@ struct Fwd64 {
     static_assert(X_IPW <= 64, "one item per lane");
     static_assert(NPT <= 32, "P tiles fit a 32-bit wave mask");
     static_assert(XP <= WAVES, "at most one extra (M-tile, N-tile) pair per wave");
+    static_assert(NKZ <= 32, "momentum sets of a tile fit a 32-bit mask");
 };
 
 // Static deal of the P tiles of a chunk to waves: each tile goes to a wave on
@@ -139,6 +141,46 @@ struct PTileDeal {
         }
         for (int w = 0; w < C::WAVES; ++w)
             if (count[w] > maxper) maxper = count[w];
+    }
+};
+
+// Phases of the end-of-block scatter into the output ring.  A tile's
+// contributions land on ring entries of the momenta k its rows carry, so tiles
+// of different waves whose k sets are disjoint can add concurrently without
+// touching the same entry; every entry then receives its additions in a fixed
+// order and the fp64 sums are bitwise reproducible.  Greedy first fit, own
+// tiles before extra pairs.
+template <class C>
+struct ScatterPlan {
+    int own_phase[C::WAVES];
+    int ext_phase[C::WAVES];
+    int nphase;
+    static constexpr uint32_t kmask(int mt) {
+        uint32_t m = 0;
+        for (int row = 16 * mt; row < 16 * mt + 16 && row < C::MROWS; ++row) m |= 1u << ((row >> 1) / C::NWV);
+        return m;
+    }
+    constexpr ScatterPlan() : own_phase{}, ext_phase{}, nphase(0) {
+        uint32_t used[2 * C::WAVES] = {};     // k set of each phase
+        int owner[2 * C::WAVES][C::WAVES] = {};  // per phase: k set contributed by each wave
+        for (int item = 0; item < 2 * C::WAVES; ++item) {
+            const int w = item % C::WAVES;
+            const bool ext = item >= C::WAVES;
+            if (ext ? !(w < C::XP) : !(w < C::OWN)) {
+                (ext ? ext_phase : own_phase)[w] = -1;
+                continue;
+            }
+            const uint32_t m = kmask(ext ? C::WAVES + w / C::NT : w);
+            int p = 0;
+            for (;; ++p) {
+                const uint32_t others = used[p] & ~(uint32_t)owner[p][w];
+                if ((others & m) == 0) break;
+            }
+            used[p] |= m;
+            owner[p][w] |= (int)m;
+            (ext ? ext_phase : own_phase)[w] = p;
+            if (p + 1 > nphase) nphase = p + 1;
+        }
     }
 };
 
@@ -410,12 +452,13 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
             }
         }
     };
-    auto scatter = [&](int blk) {
-        if (has_own) {
+    constexpr ScatterPlan<C> plan{};
+    auto scatter = [&](int blk, int phase) {
+        if (has_own && plan.own_phase[wave] == phase) {
 #pragma unroll
             for (int nt = 0; nt < C::NT; ++nt) scatter_tile(blk, own_mt, nt, acc[nt]);
         }
-        if (has_extra) scatter_tile(blk, ext_mt, ext_nt, acc_x);
+        if (has_extra && plan.ext_phase[wave] == phase) scatter_tile(blk, ext_mt, ext_nt, acc_x);
     };
 
     // ---- scale by alpha and store output planes [e_lo, e_hi); clear their ring slots
@@ -471,9 +514,8 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
             }
             __syncthreads();
         }
-        // fixed wave order keeps the fp64 sums bitwise reproducible
-        for (int w = 0; w < C::WAVES; ++w) {
-            if (wave == w) scatter(blk);
+        for (int ph = 0; ph < plan.nphase; ++ph) {
+            scatter(blk, ph);
             __syncthreads();
         }
         write_planes(blk * EB - NW, (blk + 1) * EB - NW);
