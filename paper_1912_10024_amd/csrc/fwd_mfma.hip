@@ -89,7 +89,12 @@ struct Fwd64 {
     static constexpr int XP = MT > WAVES ? (MT - WAVES) * NT : 0;
     // LDS carve-up: D table and P chunks in the operand type, the rest in doubles
     static constexpr int L_D = ZOFF + NP * 36 + 4;
-    static constexpr int L_A = NB * 3 * NN * 2;
+    // grad H in LDS: one block per neighbour pair ([nl][i][r][t] complex, a padding
+    // slot of an odd Nb stays zero), each followed by a zero tail that padding
+    // lanes of the P tiles read
+    static constexpr int ZT = 2 * NORB + 2;
+    static constexpr int PSTR = 2 * 3 * NN * 2 + ZT;
+    static constexpr int L_A = NP * PSTR;
     // two P buffers; the slot after each takes the padding results of the P tiles
     static constexpr int PBS = KR * NCP + 2;
     static constexpr int TRASH = KR * NCP;
@@ -213,6 +218,7 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
 
     // ---- stage the atom's D table, grad H; clear buffers
     for (int x = tid; x < C::L_D; x += C::THREADS) sD[x] = T(0);
+    for (int x = tid; x < C::L_A; x += C::THREADS) sA[x] = 0.0;
     __syncthreads();
     for (int x = tid; x < NKZ * NW * NB * 9; x += C::THREADS) {
         const int ij = x % 9, n = (x / 9) % NB, w = (x / (9 * NB)) % NW, q = x / (9 * NB * NW);
@@ -222,8 +228,9 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     }
     for (int x = tid; x < NB * 3 * C::NN; x += C::THREADS) {
         const cd v = cload(Ag, off_A(d, a, 0, 0) + x);
-        sA[2 * x] = v.re;
-        sA[2 * x + 1] = v.im;
+        const int n = x / (3 * C::NN), o = (n >> 1) * C::PSTR + (n & 1) * 3 * C::NN * 2 + 2 * (x % (3 * C::NN));
+        sA[o] = v.re;
+        sA[o + 1] = v.im;
     }
     for (int x = tid; x < C::L_P; x += C::THREADS) sP[x] = T(0);
     for (int x = tid; x < C::L_R; x += C::THREADS) sR[x] = 0.0;
@@ -239,15 +246,19 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     const bool x_lane = lane < C::X_IPW && x_item < C::X_ITEMS;
     const int x_u = x_item % NORB, x_i = (x_item / NORB) % 3, x_nl = (x_item / (3 * NORB)) % 2,
               x_el = x_item / (6 * NORB);
-    // neighbour atom of this lane's slot in each pair, -1 if the slot is padding
-    // or the table entry lies outside [0, na) (such a neighbour contributes zero)
+    // neighbour atom of this lane's slot in each pair: its offset into G (in
+    // doubles) and whether it is valid (a padding slot or an entry outside
+    // [0, na) contributes zero)
     const int64_t na = d.na, g_stride = d.gs * C::NN;
-    int32_t nb_of[C::NP];
+    const int64_t e_step = 2 * g_stride * na, kp_step = e_step * NE;
+    int64_t b_off[C::NP];
+    bool b_ok[C::NP];
 #pragma unroll
     for (int p = 0; p < C::NP; ++p) {
         const int n = 2 * p + x_nl;
         const int32_t b = n < NB ? nbr[a * NB + n] : -1;
-        nb_of[p] = (b >= 0 && b < na) ? b : -1;
+        b_ok[p] = x_lane && b >= 0 && b < na;
+        b_off[p] = b_ok[p] ? 2 * g_stride * b + 2 * x_u : 0;
     }
     // Branch-free gather: an invalid lane loads from the start of G (in bounds)
     // and finish_x writes zero for it.
@@ -257,22 +268,25 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
         const int gg = g < niter ? g : 0;
         const int blk = gg / C::NCHUNK;
         const int ch = gg % C::NCHUNK, kp = ch / C::NP, np = ch % C::NP;
-        int32_t b = nb_of[0];
+        int64_t off = b_off[0];
+        bool ok = b_ok[0];
 #pragma unroll
-        for (int p = 1; p < C::NP; ++p) b = np == p ? nb_of[p] : b;
+        for (int p = 1; p < C::NP; ++p) {
+            off = np == p ? b_off[p] : off;
+            ok = np == p ? b_ok[p] : ok;
+        }
         const int e = blk * EB + x_el;
-        g_ok = g < niter && x_lane && b >= 0 && e < NE;
-        const int64_t off = g_ok ? (((int64_t)kp * NE + e) * na + b) * g_stride : 0;
-        const double* Gb = G + 2 * off;
+        g_ok = g < niter && ok && e < NE;
+        off += kp * kp_step + (int64_t)e * e_step;
+        const double* Gb = G + (g_ok ? off : 0);
 #pragma unroll
-        for (int t = 0; t < NORB; ++t) gv[t] = cload(Gb, t * NORB + x_u);
+        for (int t = 0; t < NORB; ++t) gv[t] = cd{Gb[2 * t * NORB], Gb[2 * t * NORB + 1]};
     };
     // ---- X rows, step 2: X[el][nl][i][u] = sum_t gradH[n][i][r][t] G[t][u]
     auto finish_x = [&](int g) {
         if (g >= niter || !x_lane) return;
-        const int ch = g % C::NCHUNK, np = ch % C::NP;
-        const int n = 2 * np + x_nl < NB ? 2 * np + x_nl : 0;
-        const double* Ar = sA + 2 * ((n * 3 + x_i) * C::NN + r * NORB);
+        const int np = (g % C::NCHUNK) % C::NP;
+        const double* Ar = sA + np * C::PSTR + (x_nl * 3 + x_i) * C::NN * 2 + r * NORB * 2;
         cd acc{0.0, 0.0};
 #pragma unroll
         for (int t = 0; t < NORB; ++t) cfma(acc, cd{Ar[2 * t], Ar[2 * t + 1]}, gv[t]);
@@ -285,10 +299,16 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     // whole sweep (only the X/P buffer parity and the neighbour pair change)
     const uint32_t my_tiles = deal.mask[wave];
     const int my_count = deal.count[wave];
-    int pt_a[MAXT > 0 ? MAXT : 1];       // X-embedding offset (doubles), -1: zero operand
-    int pt_b[MAXT > 0 ? MAXT : 1];       // conj(grad H) offset for the first pair, -1: zero
-    int pt_nl[MAXT > 0 ? MAXT : 1];
-    int pt_out[MAXT > 0 ? MAXT : 1][4];  // P offsets of the four results (padding: the spare slot)
+    // Real embedding of P = X . grad_j H^H with B = (Re, Im) of conj(grad H): the
+    // sign of the Im part is moved onto A, whose (Im row, Im column) entry then
+    // carries the only negation.  Rows past the X rows read the zero tail of the
+    // first grad H block, and so do columns past the 3 Norb (j, c) columns.
+    constexpr bool A_PAD = C::PM_ROWS % 16 != 0;
+    constexpr int ZTAIL = 2 * 3 * C::NN * 2;  // offset of the zero tail inside a pair block
+    int pt_a[MAXT > 0 ? MAXT : 1];        // X-embedding offset (doubles) in an X buffer
+    bool pt_aok[MAXT > 0 ? MAXT : 1];     // false: the row is padding
+    int pt_b[MAXT > 0 ? MAXT : 1];        // grad H offset (doubles) in a pair block
+    int pt_out[MAXT > 0 ? MAXT : 1][4];   // P offsets of the four results (padding: the spare slot)
     bool pt_neg[MAXT > 0 ? MAXT : 1];
     {
         uint32_t rest = my_tiles;
@@ -299,12 +319,13 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
             const int nt_p = t % C::PNT, mt_p = (t / C::PNT) % C::PMT, nl = t / (C::PNT * C::PMT);
             const int arow = 16 * mt_p + j16;
             const int am = arow >> 1, arho = arow & 1, ael = am / 3, ai = am % 3;
-            pt_a[si] = arow < C::PM_ROWS ? 2 * (((ael * 2 + nl) * 3 + ai) * NORB) + (arho ^ kap) : -1;
-            pt_neg[si] = arho == 0 && kap == 1;
+            // K index 4 ks + kk = (u = 2 ks + kk/2, re/im = kap)
+            pt_aok[si] = arow < C::PM_ROWS;
+            pt_a[si] = 2 * (((ael * 2 + nl) * 3 + ai) * NORB) + (arho ^ kap) + 2 * (kk >> 1);
+            pt_neg[si] = arho == 1 && kap == 1;
             const int bcol = 16 * nt_p + j16;
             const int bj = bcol / NORB, bc = bcol % NORB;
-            pt_b[si] = bcol < C::PNC ? 2 * ((nl * 3 + bj) * C::NN + bc * NORB) + kap : -1;
-            pt_nl[si] = nl;
+            pt_b[si] = (bcol < C::PNC ? ((nl * 3 + bj) * C::NN + bc * NORB) * 2 : ZTAIL) + kap + 2 * (kk >> 1);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = 16 * mt_p + O::row_of(lane, v);
@@ -312,36 +333,33 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
                 pt_out[si][v] = (row < C::PM_ROWS && bcol < C::PNC)
                                     ? (((nl * 3 + i) * 3 + bj) * 2 + rho) * C::NCP + el * NORB + bc
                                     : C::TRASH;
-
             }
         }
     }
     auto p_tiles = [&](int g) {
         if (g >= niter) return;
         const int np = (g % C::NCHUNK) % C::NP;
-        const double* X = sX + (g & 1) * C::XB;
+        const double* Xb = sX + (g & 1) * C::XB;
+        const double* Ab = sA + np * C::PSTR;
         T* P = sP + (g & 1) * C::PBS;
 #pragma unroll
         for (int si = 0; si < MAXT; ++si) {
             if (si < my_count) {
-                const bool n_ok = 2 * np + pt_nl[si] < NB;
-                const bool a_ok = pt_a[si] >= 0, b_ok = pt_b[si] >= 0 && n_ok;
-                const double* xa = X + (a_ok ? pt_a[si] : 0);
-                const double* ab = sA + (b_ok ? pt_b[si] + np * (2 * 3 * C::NN * 2) : 0);
+                const double* xa = (!A_PAD || pt_aok[si]) ? Xb + pt_a[si] : sA + ZTAIL;
+                const double* ab = Ab + pt_b[si];
                 typename O::Acc acc{};
 #pragma unroll
                 for (int ks = 0; ks < C::PKS; ++ks) {
-                    const int u = 2 * ks + (kk >> 1);  // K index 4ks+kk = (u, re/im)
-                    const bool u_ok = u < NORB;
-                    const double xv = xa[u_ok ? 2 * u : 0];
-                    const double bvv = ab[u_ok ? 2 * u : 0];
-                    const T av = (a_ok && u_ok) ? O::neg_if(T(xv), pt_neg[si]) : T(0);
-                    const T bv = (b_ok && u_ok) ? T(kap ? -bvv : bvv) : T(0);
-                    acc = O::mma(av, bv, acc);
+                    double xv = xa[4 * ks], bv = ab[4 * ks];
+                    if constexpr (NORB % 2 != 0) {  // the last k-step runs past u = Norb - 1
+                        const bool u_ok = 2 * ks + (kk >> 1) < NORB;
+                        xv = u_ok ? xv : 0.0;
+                        bv = u_ok ? bv : 0.0;
+                    }
+                    acc = O::mma(O::neg_if(T(xv), pt_neg[si]), T(bv), acc);
                 }
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    P[pt_out[si][v]] = T(acc[v]);
+                for (int v = 0; v < 4; ++v) P[pt_out[si][v]] = T(acc[v]);
             }
         }
     };
@@ -372,7 +390,8 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     f64x4 acc[C::NT];
     f64x4 acc_x;
     auto a_ptr = [&](int k, int base, bool pad, int kp, int np) -> const T* {
-        const int q = (k - kp + NKZ) % NKZ;
+        int q = k - kp;
+        q += q < 0 ? NKZ : 0;
         return sD + (pad ? C::ZOFF : q * C::QS) + base + np * 36;
     };
     // The A operands of the chunk are loaded up front and the B operands one
