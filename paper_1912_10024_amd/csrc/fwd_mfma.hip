@@ -453,22 +453,30 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     };
 
     // ---- add one V tile of energy block blk into the output ring
+    // Branch-free: a contribution that falls off the energy grid, or comes from a
+    // padding row or column, adds 0.0 to an in-range ring entry of the tile's own
+    // k set (exact, and no entry of another concurrently scattering wave).
     auto scatter_tile = [&](int blk, int mt, int nt, const f64x4& v4) {
+        const int col = 16 * nt + j16;
+        const bool col_ok = col < C::NCOLS;
+        const int el = col_ok ? col / NORB : 0, c = col_ok ? col % NORB : 0;
+        const int es = blk * EB + el;
+        const bool e_ok = col_ok && es < NE;
+        int pbase = (blk * EB) % C::RING + el;  // ring slot of es
+        pbase -= pbase >= C::RING ? C::RING : 0;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = 16 * mt + O::row_of(lane, v);
-            const int col = 16 * nt + j16;
-            if (row < C::MROWS && col < C::NCOLS) {
-                const int rho = row & 1, kw = row >> 1, k = kw / NW, w = kw % NW + 1;
-                const int el = col / NORB, c = col % NORB;
-                const int es = blk * EB + el;
-                if (es < NE) {
-                    const int lo = es - w, hi = es + w;
-                    const int off = (k * NORB + c) * 2 + rho;
-                    if (lo >= 0) atomicAdd(&sR[(lo % C::RING) * C::RP + off], v4[v]);
-                    if (hi < NE) atomicAdd(&sR[(hi % C::RING) * C::RP + off], v4[v]);
-                }
-            }
+            const bool row_ok = row < C::MROWS, ok = e_ok && row_ok;
+            // padding rows (last M-tile only) take the last real row's momentum,
+            // which is in that tile's k set
+            const int rho = row & 1, kw = row_ok ? row >> 1 : C::MROWS / 2 - 1, k = kw / NW, w = kw % NW + 1;
+            const int off = (k * NORB + c) * 2 + rho;
+            int plo = pbase - w, phi = pbase + w;
+            plo += plo < 0 ? C::RING : 0;
+            phi -= phi >= C::RING ? C::RING : 0;
+            atomicAdd(&sR[plo * C::RP + off], (ok && es - w >= 0) ? v4[v] : 0.0);
+            atomicAdd(&sR[phi * C::RP + off], (ok && es + w < NE) ? v4[v] : 0.0);
         }
     };
     constexpr ScatterPlan<C> plan{};
