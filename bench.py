@@ -26,6 +26,7 @@ if ROOT not in sys.path:
 
 FP64_MFMA_PEAK = 78.6e12   # MI355X dense fp64 matrix peak, flop/s
 FP32_MFMA_PEAK = 157.3e12
+FP16_MFMA_PEAK = 2.5e15    # dense fp16 matrix peak
 HBM_PEAK = 8.0e12
 
 
@@ -35,7 +36,7 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--config", default="device", choices=["tiny", "mid", "device"])
-    p.add_argument("--forms", default="fp64,fp32",
+    p.add_argument("--forms", default="fp64,fp32,fp16x2",
                    help="comma-separated operand precisions to time; the first is the headline value")
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle baseline sample")
     p.add_argument("--no-cpu", action="store_true")
@@ -176,14 +177,16 @@ def main():
 
     f_eff = flops.f_eff(d)
     gemm = flops.pd_mfma_flops(d)
-    peaks = {"fp64": FP64_MFMA_PEAK, "fp32": FP32_MFMA_PEAK}
+    peaks = {"fp64": FP64_MFMA_PEAK, "fp32": FP32_MFMA_PEAK, "fp16x2": FP16_MFMA_PEAK}
+    # fp16x2: the four hi/lo partial products of the P.D GEMM on the fp16 matrix cores
+    mfma_flops = {"fp64": gemm, "fp32": gemm, "fp16x2": 4 * flops.pd_gemm_flops(d)}
     outputs, res = {}, {}
     for form in forms:
         S = torch.empty(d.sigma_shape, dtype=torch.complex128, device=dev)
         ws = sse.workspace(d, form, device=dev)
         wall, kern_ms = time_form(sse, G, D, dH, nbr, S, ws, form, args.steps, args.warmup, dev)
         ms = float(np.mean(kern_ms))
-        achieved = gemm / (ms * 1e-3)
+        achieved = mfma_flops[form] / (ms * 1e-3)
         res[form] = {
             "value": f_eff / (ms * 1e-3) / 1e12,
             "ms_per_step": wall * 1e3 / args.steps,
@@ -191,8 +194,9 @@ def main():
             "kernel_ms_all": [round(x, 3) for x in kern_ms],
             "roofline": {"bound": "mfma", "achieved": round(achieved / 1e12, 3), "peak": peaks[form] / 1e12,
                          "unit": "TFLOP/s", "frac": round(achieved / peaks[form], 4), "traffic": None,
-                         "flops_per_launch": gemm,
-                         "what": f"useful {form} matrix-core flops: P.D GEMM + P = X.gradH^H products"},
+                         "flops_per_launch": mfma_flops[form],
+                         "what": (f"useful {form} matrix-core flops: P.D GEMM + P = X.gradH^H products"
+                                  if form != "fp16x2" else "fp16 matrix-core flops of the P.D GEMM (4 hi/lo products)")},
         }
         outputs[form] = S
     head = forms[0]

@@ -81,9 +81,16 @@ typedef struct sse_dims {
 
 enum sse_precision {
     SSE_FP64 = 0,    /* fp64 products on matrix cores, fp64 reduction                  */
-    SSE_FP32 = 1     /* operands of the dense products rounded to fp32 after the fp64
+    SSE_FP32 = 1,    /* operands of the dense products rounded to fp32 after the fp64
                         gather, fp32 matrix cores, each 36-term K chunk accumulated in
                         fp32 then added in fp64; fp64 (qz, w, +/-) reduction            */
+    SSE_FP16X2 = 2   /* the paper's half-precision scheme (Sec. "Mixed Precision") with
+                        compensation: D, grad H and the left products normalised by
+                        powers of two (per atom; per K chunk and source energy), every
+                        operand of the dense product split into fp16 hi + lo, the four
+                        partial products on the fp16 matrix cores, each K chunk
+                        accumulated in fp32, unscaled and added in fp64; fp64 gather
+                        and (qz, w, +/-) reduction                                       */
 };
 
 enum sse_status {

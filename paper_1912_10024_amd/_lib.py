@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsse.so")
 
 SSE_OK, SSE_ERR_NULL, SSE_ERR_DIMS, SSE_ERR_WORKSPACE, SSE_ERR_PRECISION, SSE_ERR_HIP, SSE_ERR_NBR = range(7)
-PRECISIONS = {"fp64": 0, "fp32": 1}
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp16x2": 2}
 EXPORTS = ("sse_abi_version", "sse_last_error", "sse_workspace_bytes", "sse_effective_flops",
            "sse_forward", "sse_backward", "sse_check_nbr", "sse_combine_d")
 

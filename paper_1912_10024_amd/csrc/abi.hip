@@ -73,7 +73,7 @@ int sse_workspace_bytes(const sse_dims* dims, int precision, int backward, size_
     int rc = check_dims(dims);
     if (rc) return rc;
     if (!bytes) return fail(SSE_ERR_NULL, "bytes is NULL");
-    if (backward == 0 && precision != SSE_FP64 && precision != SSE_FP32)
+    if (backward == 0 && precision != SSE_FP64 && precision != SSE_FP32 && precision != SSE_FP16X2)
         return fail(SSE_ERR_PRECISION, "unknown precision %d", precision);
     if (backward < 0 || backward > 2) return fail(SSE_ERR_DIMS, "op must be 0 (forward), 1 (backward) or 2 (combine_d)");
     size_t ws = 256;  // status flag of sse_check_nbr
@@ -105,7 +105,7 @@ int sse_forward(const sse_dims* dims, const double* G, const double* D, const do
     int rc = check_dims(dims);
     if (rc) return rc;
     if (!G || !D || !dH || !nbr || !Sigma) return fail(SSE_ERR_NULL, "a tensor pointer is NULL");
-    if (precision != SSE_FP64 && precision != SSE_FP32)
+    if (precision != SSE_FP64 && precision != SSE_FP32 && precision != SSE_FP16X2)
         return fail(SSE_ERR_PRECISION, "unknown precision %d", precision);
     size_t need = 0;
     sse_workspace_bytes(dims, precision, 0, &need);
@@ -115,7 +115,7 @@ int sse_forward(const sse_dims* dims, const double* G, const double* D, const do
     const sse::cd alpha{alpha_re, alpha_im};
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e;
-    if (sse::fwd_mfma_specialised(d) && (precision == SSE_FP64 || precision == SSE_FP32)) {
+    if (sse::fwd_mfma_specialised(d)) {
         e = sse::launch_fwd_mfma(d, precision, G, D, dH, nbr, alpha, Sigma, s);
     } else {
         if (precision != SSE_FP64)

@@ -63,6 +63,52 @@ struct Oper<SSE_FP32> {
     static __device__ __forceinline__ int row_of(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+// fp16 hi/lo form: a value x (already scaled into the fp16 range) is split as
+// x ~ hi + lo with hi = fp16(x), lo = fp16(x - hi), leaving a relative error of
+// about 2^-22.  One K element of the GEMM is four fp16 values, (hi, hi, lo, lo)
+// on the A side and (hi, lo, hi, lo) on the B side, so one 16x16x16 f16 MFMA
+// step sums hi.hi + hi.lo + lo.hi + lo.lo over four K elements; the products
+// are exact in fp32 and accumulate in fp32.
+template <>
+struct Oper<SSE_FP16X2> {
+    using T = h4;
+    using Acc = f32x4;
+    static __device__ __forceinline__ Acc mma(T a, T b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0); }
+    static __device__ __forceinline__ T neg_if(T x, bool neg) {
+        u32x2 v = __builtin_bit_cast(u32x2, x);
+        const unsigned m = neg ? 0x80008000u : 0u;
+        v.x ^= m;
+        v.y ^= m;
+        return __builtin_bit_cast(T, v);
+    }
+    // the fp32 accumulator layout of the 16x16 f32 MFMAs
+    static __device__ __forceinline__ int row_of(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+__device__ __forceinline__ h4 split_a(double x) {
+    const _Float16 h = (_Float16)(float)x;
+    const _Float16 l = (_Float16)(float)(x - (double)h);
+    return h4{h, h, l, l};
+}
+__device__ __forceinline__ h4 split_b(float x) {
+    const _Float16 h = (_Float16)x;
+    const _Float16 l = (_Float16)(x - (float)h);
+    return h4{h, l, h, l};
+}
+// power of two s with m * s in [2^(t-1), 2^t) (1 for m = 0)
+__device__ __forceinline__ double pow2_scale(double m, int t) {
+    if (!(m > 0.0)) return 1.0;
+    int e;
+    frexp(m, &e);
+    return ldexp(1.0, t - e);
+}
+constexpr int ceil_log2(int x) {
+    int e = 0;
+    while ((1 << e) < x) ++e;
+    return e;
+}
+
 template <int NORB, int NKZ, int NW, int NB, int EB, int PREC>
 struct Fwd64 {
     using T = typename Oper<PREC>::T;
@@ -104,7 +150,10 @@ struct Fwd64 {
     static constexpr int RP = NKZ * NORB * 2;  // one ring plane: [k][c] complex
     static constexpr int L_R = RING * RP;
     static constexpr int OPER_DOUBLES = ((L_D + L_P) * (int)sizeof(T) + 7) / 8;
-    static constexpr size_t LDS_BYTES = sizeof(double) * (size_t)(OPER_DOUBLES + L_A + L_X + L_R);
+    // fp16 form: inverse scale per (chunk mod 4, source energy); also the scratch of
+    // the workgroup max reductions
+    static constexpr int L_S = 4 * EB > WAVES ? 4 * EB : WAVES;
+    static constexpr size_t LDS_BYTES = sizeof(double) * (size_t)(OPER_DOUBLES + L_A + L_X + L_R + L_S);
     static constexpr int X_ITEMS = EB * 2 * 3 * NORB;  // (el, nl, i, u)
     static constexpr int X_IPW = (X_ITEMS + WAVES - 1) / WAVES;
     // P chunk on the matrix cores, per neighbour of the pair: C[(el,i,re/im), (j,c)] =
@@ -206,6 +255,12 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     double* sA = lds + C::OPER_DOUBLES;
     double* sX = sA + C::L_A;
     double* sR = sX + C::L_X;
+    double* sS = sR + C::L_R;
+    constexpr bool F16 = PREC == SSE_FP16X2;
+    static_assert(!F16 || EB == C::WAVES, "fp16 form: wave w forms the X rows of source energy w");
+    // P chunks are formed on the fp64 matrix cores for the fp64 form, on the fp32
+    // ones otherwise
+    using OP = Oper<PREC == SSE_FP64 ? SSE_FP64 : SSE_FP32>;
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -217,20 +272,53 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     if (a >= d.na) return;  // uniform for the whole workgroup, before any barrier
 
     // ---- stage the atom's D table, grad H; clear buffers
+    // fp16 form: per-atom power-of-two normalisation of D (largest part below
+    // 2^7) and of grad H (below 2); workgroup max of the parts first
+    double sc_d = 1.0, sc_h = 1.0, inv_base = 1.0;
+    if constexpr (F16) {
+        auto block_max = [&](double m) {
+            for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+            __syncthreads();
+            if (lane == 0) sS[wave] = m;
+            __syncthreads();
+            double r = sS[0];
+            for (int w = 1; w < C::WAVES; ++w) r = fmax(r, sS[w]);
+            return r;
+        };
+        double md = 0.0, mh = 0.0;
+        for (int x = tid; x < NKZ * NW * NB * 9; x += C::THREADS) {
+            const int ij = x % 9, n = (x / 9) % NB, w = (x / (9 * NB)) % NW, q = x / (9 * NB * NW);
+            const cd v = cload(Dg, off_D(d, q, w, a, n) + ij);
+            md = fmax(md, fmax(fabs(v.re), fabs(v.im)));
+        }
+        for (int x = tid; x < NB * 3 * C::NN; x += C::THREADS) {
+            const cd v = cload(Ag, off_A(d, a, 0, 0) + x);
+            mh = fmax(mh, fmax(fabs(v.re), fabs(v.im)));
+        }
+        sc_d = pow2_scale(block_max(md), 7);
+        sc_h = pow2_scale(block_max(mh), 1);
+        inv_base = 1.0 / (sc_d * sc_h * sc_h);
+    }
     for (int x = tid; x < C::L_D; x += C::THREADS) sD[x] = T(0);
     for (int x = tid; x < C::L_A; x += C::THREADS) sA[x] = 0.0;
     __syncthreads();
     for (int x = tid; x < NKZ * NW * NB * 9; x += C::THREADS) {
         const int ij = x % 9, n = (x / 9) % NB, w = (x / (9 * NB)) % NW, q = x / (9 * NB * NW);
         const cd v = cload(Dg, off_D(d, q, w, a, n) + ij);
-        sD[q * C::QS + w * C::WS + n * 18 + ij * 2] = T(v.re);
-        sD[q * C::QS + w * C::WS + n * 18 + ij * 2 + 1] = T(v.im);
+        T* o = sD + q * C::QS + w * C::WS + n * 18 + ij * 2;
+        if constexpr (F16) {
+            o[0] = split_a(v.re * sc_d);
+            o[1] = split_a(v.im * sc_d);
+        } else {
+            o[0] = T(v.re);
+            o[1] = T(v.im);
+        }
     }
     for (int x = tid; x < NB * 3 * C::NN; x += C::THREADS) {
         const cd v = cload(Ag, off_A(d, a, 0, 0) + x);
         const int n = x / (3 * C::NN), o = (n >> 1) * C::PSTR + (n & 1) * 3 * C::NN * 2 + 2 * (x % (3 * C::NN));
-        sA[o] = v.re;
-        sA[o + 1] = v.im;
+        sA[o] = v.re * sc_h;
+        sA[o + 1] = v.im * sc_h;
     }
     for (int x = tid; x < C::L_P; x += C::THREADS) sP[x] = T(0);
     for (int x = tid; x < C::L_R; x += C::THREADS) sR[x] = 0.0;
@@ -283,16 +371,32 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
         for (int t = 0; t < NORB; ++t) gv[t] = cd{Gb[2 * t * NORB], Gb[2 * t * NORB + 1]};
     };
     // ---- X rows, step 2: X[el][nl][i][u] = sum_t gradH[n][i][r][t] G[t][u]
+    // fp16 form: the X rows of one source energy (one wave) are normalised by a
+    // power of two (largest part below 2^XT, which keeps every P entry below
+    // 2^14); the inverse of all scale factors of the chunk's column goes to LDS
+    constexpr int XT = 14 - ceil_log2(4 * NORB);
     auto finish_x = [&](int g) {
-        if (g >= niter || !x_lane) return;
+        if (g >= niter || (!F16 && !x_lane)) return;
         const int np = (g % C::NCHUNK) % C::NP;
         const double* Ar = sA + np * C::PSTR + (x_nl * 3 + x_i) * C::NN * 2 + r * NORB * 2;
         cd acc{0.0, 0.0};
 #pragma unroll
         for (int t = 0; t < NORB; ++t) cfma(acc, cd{Ar[2 * t], Ar[2 * t + 1]}, gv[t]);
+        if (!g_ok) acc = cd{0.0, 0.0};
+        if constexpr (F16) {
+            const double m = fmax(fabs(acc.re), fabs(acc.im));
+            int e = -4000;
+            if (m > 0.0) frexp(m, &e);
+            for (int o = 32; o > 0; o >>= 1) e = max(e, __shfl_xor(e, o));
+            const int shift = e == -4000 ? 0 : XT - e;
+            acc.re = ldexp(acc.re, shift);
+            acc.im = ldexp(acc.im, shift);
+            if (lane == 0) sS[(g & 3) * EB + wave] = ldexp(inv_base, -shift);
+            if (!x_lane) return;
+        }
         double* X = sX + (g & 1) * C::XB;
-        X[2 * x_item] = g_ok ? acc.re : 0.0;
-        X[2 * x_item + 1] = g_ok ? acc.im : 0.0;
+        X[2 * x_item] = acc.re;
+        X[2 * x_item + 1] = acc.im;
     };
 
     // ---- P tiles of this wave: per-lane operand and output offsets, fixed for the
@@ -328,7 +432,7 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
             pt_b[si] = (bcol < C::PNC ? ((nl * 3 + bj) * C::NN + bc * NORB) * 2 : ZTAIL) + kap + 2 * (kk >> 1);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = 16 * mt_p + O::row_of(lane, v);
+                const int row = 16 * mt_p + OP::row_of(lane, v);
                 const int m = row >> 1, rho = row & 1, el = m / 3, i = m % 3;
                 pt_out[si][v] = (row < C::PM_ROWS && bcol < C::PNC)
                                     ? (((nl * 3 + i) * 3 + bj) * 2 + rho) * C::NCP + el * NORB + bc
@@ -347,7 +451,8 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
             if (si < my_count) {
                 const double* xa = (!A_PAD || pt_aok[si]) ? Xb + pt_a[si] : sA + ZTAIL;
                 const double* ab = Ab + pt_b[si];
-                typename O::Acc acc{};
+                using TP = typename OP::T;
+                typename OP::Acc acc{};
 #pragma unroll
                 for (int ks = 0; ks < C::PKS; ++ks) {
                     double xv = xa[4 * ks], bv = ab[4 * ks];
@@ -356,10 +461,15 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
                         xv = u_ok ? xv : 0.0;
                         bv = u_ok ? bv : 0.0;
                     }
-                    acc = O::mma(O::neg_if(T(xv), pt_neg[si]), T(bv), acc);
+                    acc = OP::mma(OP::neg_if(TP(xv), pt_neg[si]), TP(bv), acc);
                 }
 #pragma unroll
-                for (int v = 0; v < 4; ++v) P[pt_out[si][v]] = T(acc[v]);
+                for (int v = 0; v < 4; ++v) {
+                    if constexpr (F16)
+                        P[pt_out[si][v]] = split_b(acc[v]);
+                    else
+                        P[pt_out[si][v]] = T(acc[v]);
+                }
             }
         }
     };
@@ -402,14 +512,11 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
         const T* Ao = a_ptr(own_k, own_base, own_pad, kp, np);
         const T* Ax = a_ptr(ext_k, ext_base, ext_pad, kp, np);
         const T* Px = Pb + 16 * ext_nt;
-        T ao[C::KS], ax[C::KS];
-#pragma unroll
-        for (int ks = 0; ks < C::KS; ++ks) {
-            // rows of a wave without such a tile are padding rows: they read zeros
-            ao[ks] = Ao[4 * ks];
-            ax[ks] = Ax[4 * ks];
-        }
-        T bv[2][C::NT], bx[2];
+        // A and B operands of k-step ks + 1 are loaded while the MFMAs of ks run
+        T ao[2], ax[2], bv[2][C::NT], bx[2];
+        // rows of a wave without such a tile are padding rows: they read zeros
+        ao[0] = Ao[0];
+        ax[0] = Ax[0];
 #pragma unroll
         for (int nt = 0; nt < C::NT; ++nt) bv[0][nt] = Pb[16 * nt];
         bx[0] = Px[0];
@@ -423,11 +530,13 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
         for (int ks = 0; ks < C::KS; ++ks) {
             const int cur = ks & 1, nxt = cur ^ 1;
             if (ks + 1 < C::KS) {
+                ao[nxt] = Ao[4 * (ks + 1)];
+                ax[nxt] = Ax[4 * (ks + 1)];
 #pragma unroll
                 for (int nt = 0; nt < C::NT; ++nt) bv[nxt][nt] = Pb[4 * (ks + 1) * C::NCP + 16 * nt];
                 bx[nxt] = Px[4 * (ks + 1) * C::NCP];
             }
-            const T a = O::neg_if(ao[ks], own_neg), b = O::neg_if(ax[ks], ext_neg);
+            const T a = O::neg_if(ao[cur], own_neg), b = O::neg_if(ax[cur], ext_neg);
             if constexpr (PREC == SSE_FP64) {
                 if (has_own) {
 #pragma unroll
@@ -442,7 +551,23 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
                 if (has_extra) part_x = O::mma(b, bx[cur], part_x);
             }
         }
-        if constexpr (PREC != SSE_FP64) {
+        if constexpr (F16) {
+            // undo the chunk's normalisation of the lane's column (source energy)
+            const double* inv = sS + (g & 3) * EB;
+            auto el_of = [&](int nt) {
+                const int col = 16 * nt + j16;
+                return col < C::NCOLS ? col / NORB : 0;
+            };
+#pragma unroll
+            for (int nt = 0; nt < C::NT; ++nt) {
+                const double f = inv[el_of(nt)];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[nt][v] = fma((double)part[nt][v], f, acc[nt][v]);
+            }
+            const double fx = inv[el_of(ext_nt)];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc_x[v] = fma((double)part_x[v], fx, acc_x[v]);
+        } else if constexpr (PREC != SSE_FP64) {
 #pragma unroll
             for (int nt = 0; nt < C::NT; ++nt)
 #pragma unroll
@@ -589,6 +714,7 @@ hipError_t launch_fwd_mfma(const Dims& d, int precision, const double* G, const 
                            const int32_t* nbr, cd alpha, double* S, hipStream_t stream) {
     if (precision == SSE_FP64) return dispatch_fwd<SSE_FP64>(d, G, D, A, nbr, alpha, S, stream);
     if (precision == SSE_FP32) return dispatch_fwd<SSE_FP32>(d, G, D, A, nbr, alpha, S, stream);
+    if (precision == SSE_FP16X2) return dispatch_fwd<SSE_FP16X2>(d, G, D, A, nbr, alpha, S, stream);
     return hipErrorInvalidValue;
 }
 

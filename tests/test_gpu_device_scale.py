@@ -40,7 +40,7 @@ def device_problem():
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-6), ("fp16x2", 1e-6)])
 def test_device_scale_sampled_parity(device_problem, precision, tol):
     d, inp = device_problem
     G, D, dH, nbr = inp["G<"], inp["D<"], inp["dH"], inp["nbr"]

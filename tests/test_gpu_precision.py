@@ -16,7 +16,7 @@ from paper_1912_10024_amd.inputs import CONFIGS, Dims, generate, make_nbr, anti_
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp32": 1e-6}
+TOL = {"fp32": 1e-6, "fp16x2": 1e-6}
 
 
 def _rand(dims: Dims, seed: int):
@@ -66,6 +66,38 @@ def test_reduced_precision_mid_sampled(precision):
     rel, blk, mx = _errs(got, ref)
     print(f"[precision] {precision} mid sampled rel_frob={rel:.3e} max_block_rel={blk:.3e}")
     assert rel <= TOL[precision]
+
+
+@pytest.mark.parametrize("sg,sd,sh", [(1e-6, 1e5, 1e-4), (1e4, 1e-7, 30.0), (1.0, 1.0, 1e-3)],
+                         ids=["small_G", "large_G", "small_dH"])
+def test_fp16_normalisation_extreme_magnitudes(sg, sd, sh):
+    """Inputs far outside the fp16 range: without the power-of-two normalisation
+    the hi/lo operands would underflow or overflow.  Sigma is linear in G and D
+    and quadratic in grad H, so the reference is the oracle's result for the
+    unscaled inputs times sg * sd * sh^2."""
+    dims = Dims(nkz=7, ne=29, nqz=7, nw=10, na=6, nb=4, norb=10, g_slots=1)
+    inp = _rand(dims, 11)
+    ref = oracle.sse_forward(dims, inp["G"], inp["D"], inp["dH"], inp["nbr"], alpha=1j) * (sg * sd * sh * sh)
+    t = {k: torch.from_numpy(v).cuda() for k, v in inp.items()}
+    S = sse.forward(t["G"] * sg, t["D"] * sd, t["dH"] * sh, t["nbr"], alpha=1j, precision="fp16x2").cpu().numpy()
+    rel, blk, mx = _errs(S, ref)
+    print(f"[precision] fp16x2 scaled G x{sg:g} D x{sd:g} dH x{sh:g} rel_frob={rel:.3e} max_block_rel={blk:.3e}")
+    assert rel <= TOL["fp16x2"]
+
+
+def test_fp16_normalisation_energy_dependent_magnitude():
+    """G spanning eight orders of magnitude across energies: the X rows are
+    normalised per K chunk and source energy, so every energy keeps ~2^-22
+    relative operand precision."""
+    dims = Dims(nkz=7, ne=33, nqz=7, nw=10, na=6, nb=4, norb=10, g_slots=1)
+    inp = _rand(dims, 12)
+    inp["G"] = inp["G"] * (10.0 ** (np.arange(dims.ne) % 9 - 4))[None, :, None, None, None, None]
+    ref = oracle.sse_forward(dims, inp["G"], inp["D"], inp["dH"], inp["nbr"], alpha=1j)
+    t = {k: torch.from_numpy(v).cuda() for k, v in inp.items()}
+    S = sse.forward(t["G"], t["D"], t["dH"], t["nbr"], alpha=1j, precision="fp16x2").cpu().numpy()
+    rel, blk, mx = _errs(S, ref)
+    print(f"[precision] fp16x2 energy-graded G rel_frob={rel:.3e} max_block_rel={blk:.3e}")
+    assert rel <= TOL["fp16x2"]
 
 
 def test_unknown_precision_rejected():
