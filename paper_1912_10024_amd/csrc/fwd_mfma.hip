@@ -103,6 +103,17 @@ __device__ __forceinline__ double pow2_scale(double m, int t) {
     frexp(m, &e);
     return ldexp(1.0, t - e);
 }
+// largest value over a full wave: butterflies inside each row of 16 lanes on
+// the DPP network, then the four row results through scalar registers
+__device__ __forceinline__ int wave_max(int v) {
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x124, 0xF, 0xF, false));  // row_ror:4
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x128, 0xF, 0xF, false));  // row_ror:8
+    const int r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+    const int r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+    return max(max(r0, r1), max(r2, r3));
+}
 constexpr int ceil_log2(int x) {
     int e = 0;
     while ((1 << e) < x) ++e;
@@ -387,7 +398,7 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
             const double m = fmax(fabs(acc.re), fabs(acc.im));
             int e = -4000;
             if (m > 0.0) frexp(m, &e);
-            for (int o = 32; o > 0; o >>= 1) e = max(e, __shfl_xor(e, o));
+            e = wave_max(e);
             const int shift = e == -4000 ? 0 : XT - e;
             acc.re = ldexp(acc.re, shift);
             acc.im = ldexp(acc.im, shift);
@@ -452,7 +463,8 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
                 const double* xa = (!A_PAD || pt_aok[si]) ? Xb + pt_a[si] : sA + ZTAIL;
                 const double* ab = Ab + pt_b[si];
                 using TP = typename OP::T;
-                typename OP::Acc acc{};
+                // two accumulators (even and odd k-steps) halve the dependent chain
+                typename OP::Acc acc0{}, acc1{};
 #pragma unroll
                 for (int ks = 0; ks < C::PKS; ++ks) {
                     double xv = xa[4 * ks], bv = ab[4 * ks];
@@ -461,8 +473,14 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
                         xv = u_ok ? xv : 0.0;
                         bv = u_ok ? bv : 0.0;
                     }
-                    acc = OP::mma(OP::neg_if(TP(xv), pt_neg[si]), TP(bv), acc);
+                    // (the fp64 MFMA is long enough to cover its own dependency)
+                    if ((ks & 1) && PREC != SSE_FP64)
+                        acc1 = OP::mma(OP::neg_if(TP(xv), pt_neg[si]), TP(bv), acc1);
+                    else
+                        acc0 = OP::mma(OP::neg_if(TP(xv), pt_neg[si]), TP(bv), acc0);
                 }
+                typename OP::Acc acc = acc0;
+                if constexpr (PREC != SSE_FP64) acc += acc1;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     if constexpr (F16)
