@@ -84,13 +84,13 @@ enum sse_precision {
     SSE_FP32 = 1,    /* operands of the dense products rounded to fp32 after the fp64
                         gather, fp32 matrix cores, each 36-term K chunk accumulated in
                         fp32 then added in fp64; fp64 (qz, w, +/-) reduction            */
-    SSE_FP16X2 = 2   /* the paper's half-precision scheme (Sec. "Mixed Precision") with
-                        compensation: D, grad H and the left products normalised by
-                        powers of two (per atom; per K chunk and source energy), every
-                        operand of the dense product split into fp16 hi + lo, the four
-                        partial products on the fp16 matrix cores, each K chunk
-                        accumulated in fp32, unscaled and added in fp64; fp64 gather
-                        and (qz, w, +/-) reduction                                       */
+    SSE_FP16X2 = 2   /* half precision with compensation (Sec. "Mixed-Precision
+                        Computation"): D, grad H and the left products normalised
+                        by powers of two (per atom; per K chunk and source energy),
+                        every operand of the dense product split into fp16 hi + lo,
+                        the four partial products on the fp16 matrix cores, each K
+                        chunk accumulated in fp32, unscaled and added in fp64; fp64
+                        gather and (qz, w, +/-) reduction                           */
 };
 
 enum sse_status {

@@ -1,4 +1,5 @@
-// FP64 matrix-core forward kernel of the scattering self-energy (Eq. 3).
+// Matrix-core forward kernel of the scattering self-energy (Eq. 3), with fp64,
+// fp32 and fp16 hi/lo GEMM operands.
 //
 // Regrouping (the fission of Sec. "Dataflow Optimizations", taken one step
 // further so the matrix cores see one dense GEMM per atom):
@@ -19,16 +20,16 @@
 // (36 real K rows = 9 MFMA k-steps).  Complex products use the real
 // embedding [[Dr, -Di], [Di, Dr]] . [Pr; Pi].
 //
-// Pipeline per chunk (one barrier): every wave issues its share of the
-// 16x16x4 fp64 MFMAs on the P chunk in LDS, forms the next P chunk from the
-// X = grad_i H . G rows of the chunk after (vector ALUs, double-buffered
-// in LDS), and gathers the G blocks for the chunk after that from HBM.  The
-// waves on one SIMD alternate which of the two they do first, so one wave's
-// vector work runs under the other's matrix instructions.  At the end of an
-// energy block each wave adds its accumulators into a ring of output planes
-// (LDS, fp64), in wave order so that results are bitwise reproducible;
-// planes that can receive no more contributions are scaled by alpha and
-// written out.
+// Pipeline per chunk (one barrier): every wave gathers the G columns of a
+// later chunk into registers, issues its share of the MFMAs on the P chunk in
+// LDS, forms P tiles of the next chunk from the X = grad_i H . G rows in LDS
+// (a second small GEMM), and forms the X rows of the chunk after that on the
+// vector ALUs (double-buffered in LDS).  The two waves of a SIMD run these
+// phases in opposite orders, so the latency-bound phases of one wave meet
+// the matrix work of the other.  At the end of an energy block the waves add
+// their accumulators into a ring of output planes (LDS, fp64) in phases that
+// touch disjoint entries, so results are bitwise reproducible; planes that
+// can receive no more contributions are scaled by alpha and written out.
 #include "sse_kernels.h"
 
 namespace sse {
