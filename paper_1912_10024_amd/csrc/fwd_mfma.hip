@@ -30,6 +30,8 @@
 // their accumulators into a ring of output planes (LDS, fp64) in phases that
 // touch disjoint entries, so results are bitwise reproducible; planes that
 // can receive no more contributions are scaled by alpha and written out.
+#include <type_traits>
+
 #include "sse_kernels.h"
 
 namespace sse {
@@ -149,15 +151,23 @@ struct Fwd64 {
     static constexpr int L_D = ZOFF + NP * 36 + 4;
     // grad H in LDS: one block per neighbour pair ([nl][i][r][t] complex, a padding
     // slot of an odd Nb stays zero), each followed by a zero tail that padding
-    // lanes of the P tiles read
+    // lanes of the P tiles read.  Rows (r) are padded to an odd number of
+    // doubles so that the 16 lanes of a P-tile operand load, which read 16
+    // consecutive (j, c) rows, hit distinct LDS banks.
+    static constexpr int AR = 2 * NORB + 1;       // doubles per grad H row
+    static constexpr int NNS = NORB * AR;         // doubles per grad H block
     static constexpr int ZT = 2 * NORB + 2;
-    static constexpr int PSTR = 2 * 3 * NN * 2 + ZT;
+    static constexpr int PSTR = 2 * 3 * NNS + ZT;
     static constexpr int L_A = NP * PSTR;
     // two P buffers; the slot after each takes the padding results of the P tiles
     static constexpr int PBS = KR * NCP + 2;
     static constexpr int TRASH = KR * NCP;
     static constexpr int L_P = 2 * PBS;
-    static constexpr int XB = EB * 2 * 3 * NORB * 2;  // one X buffer: [el][nl][i][u] complex
+    // one X buffer: rows [nl][el][i] of Norb complex, padded to XR doubles so that
+    // the rows a P tile reads (consecutive (el, i) of one nl) spread over the
+    // LDS banks, and kept even so a (re, im) pair is one 16-byte store
+    static constexpr int XR = 2 * NORB + 2;
+    static constexpr int XB = 2 * EB * 3 * XR;
     static constexpr int L_X = 2 * XB;
     static constexpr int RP = NKZ * NORB * 2;  // one ring plane: [k][c] complex
     static constexpr int L_R = RING * RP;
@@ -328,7 +338,8 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     }
     for (int x = tid; x < NB * 3 * C::NN; x += C::THREADS) {
         const cd v = cload(Ag, off_A(d, a, 0, 0) + x);
-        const int n = x / (3 * C::NN), o = (n >> 1) * C::PSTR + (n & 1) * 3 * C::NN * 2 + 2 * (x % (3 * C::NN));
+        const int n = x / (3 * C::NN), i = (x / C::NN) % 3, rc = x % C::NN;
+        const int o = (n >> 1) * C::PSTR + ((n & 1) * 3 + i) * C::NNS + (rc / NORB) * C::AR + 2 * (rc % NORB);
         sA[o] = v.re * sc_h;
         sA[o + 1] = v.im * sc_h;
     }
@@ -390,7 +401,7 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     auto finish_x = [&](int g) {
         if (g >= niter || (!F16 && !x_lane)) return;
         const int np = (g % C::NCHUNK) % C::NP;
-        const double* Ar = sA + np * C::PSTR + (x_nl * 3 + x_i) * C::NN * 2 + r * NORB * 2;
+        const double* Ar = sA + np * C::PSTR + (x_nl * 3 + x_i) * C::NNS + r * C::AR;
         cd acc{0.0, 0.0};
 #pragma unroll
         for (int t = 0; t < NORB; ++t) cfma(acc, cd{Ar[2 * t], Ar[2 * t + 1]}, gv[t]);
@@ -406,9 +417,8 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
             if (lane == 0) sS[(g & 3) * EB + wave] = ldexp(inv_base, -shift);
             if (!x_lane) return;
         }
-        double* X = sX + (g & 1) * C::XB;
-        X[2 * x_item] = acc.re;
-        X[2 * x_item + 1] = acc.im;
+        double2* X = reinterpret_cast<double2*>(sX + (g & 1) * C::XB + ((x_nl * EB + x_el) * 3 + x_i) * C::XR) + x_u;
+        *X = make_double2(acc.re, acc.im);
     };
 
     // ---- P tiles of this wave: per-lane operand and output offsets, fixed for the
@@ -420,7 +430,7 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     // carries the only negation.  Rows past the X rows read the zero tail of the
     // first grad H block, and so do columns past the 3 Norb (j, c) columns.
     constexpr bool A_PAD = C::PM_ROWS % 16 != 0;
-    constexpr int ZTAIL = 2 * 3 * C::NN * 2;  // offset of the zero tail inside a pair block
+    constexpr int ZTAIL = 2 * 3 * C::NNS;  // offset of the zero tail inside a pair block
     int pt_a[MAXT > 0 ? MAXT : 1];        // X-embedding offset (doubles) in an X buffer
     bool pt_aok[MAXT > 0 ? MAXT : 1];     // false: the row is padding
     int pt_b[MAXT > 0 ? MAXT : 1];        // grad H offset (doubles) in a pair block
@@ -437,11 +447,11 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
             const int am = arow >> 1, arho = arow & 1, ael = am / 3, ai = am % 3;
             // K index 4 ks + kk = (u = 2 ks + kk/2, re/im = kap)
             pt_aok[si] = arow < C::PM_ROWS;
-            pt_a[si] = 2 * (((ael * 2 + nl) * 3 + ai) * NORB) + (arho ^ kap) + 2 * (kk >> 1);
+            pt_a[si] = ((nl * EB + ael) * 3 + ai) * C::XR + (arho ^ kap) + 2 * (kk >> 1);
             pt_neg[si] = arho == 1 && kap == 1;
             const int bcol = 16 * nt_p + j16;
             const int bj = bcol / NORB, bc = bcol % NORB;
-            pt_b[si] = (bcol < C::PNC ? ((nl * 3 + bj) * C::NN + bc * NORB) * 2 : ZTAIL) + kap + 2 * (kk >> 1);
+            pt_b[si] = (bcol < C::PNC ? (nl * 3 + bj) * C::NNS + bc * C::AR : ZTAIL) + kap + 2 * (kk >> 1);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = 16 * mt_p + OP::row_of(lane, v);
@@ -452,44 +462,68 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
             }
         }
     }
+    // N tiles starting at slot s0, processed together so that their operand
+    // loads and MFMA chains interleave
+    auto p_tile_group = [&](auto n_const, int s0, const double* Xb, const double* Ab, T* P) {
+        constexpr int N = decltype(n_const)::value;
+        using TP = typename OP::T;
+        const double* xa[N];
+        const double* ab[N];
+#pragma unroll
+        for (int t = 0; t < N; ++t) {
+            xa[t] = (!A_PAD || pt_aok[s0 + t]) ? Xb + pt_a[s0 + t] : sA + ZTAIL;
+            ab[t] = Ab + pt_b[s0 + t];
+        }
+        // two accumulators per tile (even and odd k-steps) halve the dependent
+        // chain of the fp32 MFMAs; the fp64 MFMA covers its own dependency
+        typename OP::Acc acc0[N], acc1[N];
+#pragma unroll
+        for (int t = 0; t < N; ++t) acc0[t] = acc1[t] = typename OP::Acc{};
+#pragma unroll
+        for (int ks = 0; ks < C::PKS; ++ks) {
+#pragma unroll
+            for (int t = 0; t < N; ++t) {
+                double xv = xa[t][4 * ks], bv = ab[t][4 * ks];
+                if constexpr (NORB % 2 != 0) {  // the last k-step runs past u = Norb - 1
+                    const bool u_ok = 2 * ks + (kk >> 1) < NORB;
+                    xv = u_ok ? xv : 0.0;
+                    bv = u_ok ? bv : 0.0;
+                }
+                if ((ks & 1) && PREC != SSE_FP64)
+                    acc1[t] = OP::mma(OP::neg_if(TP(xv), pt_neg[s0 + t]), TP(bv), acc1[t]);
+                else
+                    acc0[t] = OP::mma(OP::neg_if(TP(xv), pt_neg[s0 + t]), TP(bv), acc0[t]);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < N; ++t) {
+            typename OP::Acc acc = acc0[t];
+            if constexpr (PREC != SSE_FP64) acc += acc1[t];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                if constexpr (F16)
+                    P[pt_out[s0 + t][v]] = split_b(acc[v]);
+                else
+                    P[pt_out[s0 + t][v]] = T(acc[v]);
+            }
+        }
+    };
     auto p_tiles = [&](int g) {
         if (g >= niter) return;
         const int np = (g % C::NCHUNK) % C::NP;
         const double* Xb = sX + (g & 1) * C::XB;
         const double* Ab = sA + np * C::PSTR;
         T* P = sP + (g & 1) * C::PBS;
+        // tiles in pairs, a last single one if the wave's count is odd
 #pragma unroll
-        for (int si = 0; si < MAXT; ++si) {
-            if (si < my_count) {
-                const double* xa = (!A_PAD || pt_aok[si]) ? Xb + pt_a[si] : sA + ZTAIL;
-                const double* ab = Ab + pt_b[si];
-                using TP = typename OP::T;
-                // two accumulators (even and odd k-steps) halve the dependent chain
-                typename OP::Acc acc0{}, acc1{};
-#pragma unroll
-                for (int ks = 0; ks < C::PKS; ++ks) {
-                    double xv = xa[4 * ks], bv = ab[4 * ks];
-                    if constexpr (NORB % 2 != 0) {  // the last k-step runs past u = Norb - 1
-                        const bool u_ok = 2 * ks + (kk >> 1) < NORB;
-                        xv = u_ok ? xv : 0.0;
-                        bv = u_ok ? bv : 0.0;
-                    }
-                    // (the fp64 MFMA is long enough to cover its own dependency)
-                    if ((ks & 1) && PREC != SSE_FP64)
-                        acc1 = OP::mma(OP::neg_if(TP(xv), pt_neg[si]), TP(bv), acc1);
-                    else
-                        acc0 = OP::mma(OP::neg_if(TP(xv), pt_neg[si]), TP(bv), acc0);
-                }
-                typename OP::Acc acc = acc0;
-                if constexpr (PREC != SSE_FP64) acc += acc1;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    if constexpr (F16)
-                        P[pt_out[si][v]] = split_b(acc[v]);
-                    else
-                        P[pt_out[si][v]] = T(acc[v]);
+        for (int s0 = 0; s0 < MAXT; s0 += 2) {
+            if constexpr (MAXT >= 2) {
+                if (s0 + 2 <= my_count) {
+                    p_tile_group(std::integral_constant<int, 2>{}, s0, Xb, Ab, P);
+                    continue;
                 }
             }
+            if (s0 < my_count) p_tile_group(std::integral_constant<int, 1>{}, s0, Xb, Ab, P);
         }
     };
 
