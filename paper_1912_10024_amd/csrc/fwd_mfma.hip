@@ -94,10 +94,12 @@ __device__ __forceinline__ h4 split_a(double x) {
     const _Float16 l = (_Float16)(float)(x - (double)h);
     return h4{h, h, l, l};
 }
-__device__ __forceinline__ h4 split_b(float x) {
+// (hi, lo) as one 32-bit word; the B entry (hi, lo, hi, lo) is that word twice
+__device__ __forceinline__ unsigned split_b_word(float x) {
     const _Float16 h = (_Float16)x;
     const _Float16 l = (_Float16)(x - (float)h);
-    return h4{h, l, h, l};
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(unsigned, h2{h, l});
 }
 // power of two s with m * s in [2^(t-1), 2^t) (1 for m = 0)
 __device__ __forceinline__ double pow2_scale(double m, int t) {
@@ -168,14 +170,19 @@ struct Fwd64 {
     // LDS banks, and kept even so a (re, im) pair is one 16-byte store
     static constexpr int XR = 2 * NORB + 2;
     static constexpr int XB = 2 * EB * 3 * XR;
-    static constexpr int L_X = 2 * XB;
+    // P tiles run on fp64 MFMAs for the fp64 form and on fp32 MFMAs otherwise;
+    // their operands (X rows and a copy of grad H) are stored in that type
+    using TPT = typename Oper<PREC == SSE_FP64 ? SSE_FP64 : SSE_FP32>::T;
+    static constexpr bool SPLIT_A = PREC != SSE_FP64;
+    static constexpr int L_X = (2 * XB * (int)sizeof(TPT) + 7) / 8;
+    static constexpr int L_AP = SPLIT_A ? (L_A * (int)sizeof(TPT) + 7) / 8 : 0;
     static constexpr int RP = NKZ * NORB * 2;  // one ring plane: [k][c] complex
     static constexpr int L_R = RING * RP;
     static constexpr int OPER_DOUBLES = ((L_D + L_P) * (int)sizeof(T) + 7) / 8;
     // fp16 form: inverse scale per (chunk mod 4, source energy); also the scratch of
     // the workgroup max reductions
     static constexpr int L_S = 4 * EB > WAVES ? 4 * EB : WAVES;
-    static constexpr size_t LDS_BYTES = sizeof(double) * (size_t)(OPER_DOUBLES + L_A + L_X + L_R + L_S);
+    static constexpr size_t LDS_BYTES = sizeof(double) * (size_t)(OPER_DOUBLES + L_A + L_AP + L_X + L_R + L_S);
     static constexpr int X_ITEMS = EB * 2 * 3 * NORB;  // (el, nl, i, u)
     static constexpr int X_IPW = (X_ITEMS + WAVES - 1) / WAVES;
     // P chunk on the matrix cores, per neighbour of the pair: C[(el,i,re/im), (j,c)] =
@@ -274,15 +281,17 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     extern __shared__ double lds[];
     T* sD = reinterpret_cast<T*>(lds);
     T* sP = sD + C::L_D;
-    double* sA = lds + C::OPER_DOUBLES;
-    double* sX = sA + C::L_A;
-    double* sR = sX + C::L_X;
-    double* sS = sR + C::L_R;
-    constexpr bool F16 = PREC == SSE_FP16X2;
-    static_assert(!F16 || EB == C::WAVES, "fp16 form: wave w forms the X rows of source energy w");
     // P chunks are formed on the fp64 matrix cores for the fp64 form, on the fp32
     // ones otherwise
     using OP = Oper<PREC == SSE_FP64 ? SSE_FP64 : SSE_FP32>;
+    using TP = typename OP::T;
+    double* sA = lds + C::OPER_DOUBLES;
+    TP* sAp = reinterpret_cast<TP*>(sA + (C::SPLIT_A ? C::L_A : 0));  // grad H for the P tiles
+    TP* sX = reinterpret_cast<TP*>(sA + C::L_A + C::L_AP);
+    double* sR = sA + C::L_A + C::L_AP + C::L_X;
+    double* sS = sR + C::L_R;
+    constexpr bool F16 = PREC == SSE_FP16X2;
+    static_assert(!F16 || EB == C::WAVES, "fp16 form: wave w forms the X rows of source energy w");
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -323,6 +332,8 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     }
     for (int x = tid; x < C::L_D; x += C::THREADS) sD[x] = T(0);
     for (int x = tid; x < C::L_A; x += C::THREADS) sA[x] = 0.0;
+    if constexpr (C::SPLIT_A)
+        for (int x = tid; x < C::L_A; x += C::THREADS) sAp[x] = TP(0);
     __syncthreads();
     for (int x = tid; x < NKZ * NW * NB * 9; x += C::THREADS) {
         const int ij = x % 9, n = (x / 9) % NB, w = (x / (9 * NB)) % NW, q = x / (9 * NB * NW);
@@ -342,6 +353,10 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
         const int o = (n >> 1) * C::PSTR + ((n & 1) * 3 + i) * C::NNS + (rc / NORB) * C::AR + 2 * (rc % NORB);
         sA[o] = v.re * sc_h;
         sA[o + 1] = v.im * sc_h;
+        if constexpr (C::SPLIT_A) {
+            sAp[o] = TP(v.re * sc_h);
+            sAp[o + 1] = TP(v.im * sc_h);
+        }
     }
     for (int x = tid; x < C::L_P; x += C::THREADS) sP[x] = T(0);
     for (int x = tid; x < C::L_R; x += C::THREADS) sR[x] = 0.0;
@@ -417,8 +432,11 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
             if (lane == 0) sS[(g & 3) * EB + wave] = ldexp(inv_base, -shift);
             if (!x_lane) return;
         }
-        double2* X = reinterpret_cast<double2*>(sX + (g & 1) * C::XB + ((x_nl * EB + x_el) * 3 + x_i) * C::XR) + x_u;
-        *X = make_double2(acc.re, acc.im);
+        TP* X = sX + (g & 1) * C::XB + ((x_nl * EB + x_el) * 3 + x_i) * C::XR + 2 * x_u;
+        if constexpr (C::SPLIT_A)
+            *reinterpret_cast<float2*>(X) = make_float2((float)acc.re, (float)acc.im);
+        else
+            *reinterpret_cast<double2*>(X) = make_double2(acc.re, acc.im);
     };
 
     // ---- P tiles of this wave: per-lane operand and output offsets, fixed for the
@@ -464,14 +482,13 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     }
     // N tiles starting at slot s0, processed together so that their operand
     // loads and MFMA chains interleave
-    auto p_tile_group = [&](auto n_const, int s0, const double* Xb, const double* Ab, T* P) {
+    auto p_tile_group = [&](auto n_const, int s0, const TP* Xb, const TP* Ab, T* P) {
         constexpr int N = decltype(n_const)::value;
-        using TP = typename OP::T;
-        const double* xa[N];
-        const double* ab[N];
+        const TP* xa[N];
+        const TP* ab[N];
 #pragma unroll
         for (int t = 0; t < N; ++t) {
-            xa[t] = (!A_PAD || pt_aok[s0 + t]) ? Xb + pt_a[s0 + t] : sA + ZTAIL;
+            xa[t] = (!A_PAD || pt_aok[s0 + t]) ? Xb + pt_a[s0 + t] : sAp + ZTAIL;
             ab[t] = Ab + pt_b[s0 + t];
         }
         // two accumulators per tile (even and odd k-steps) halve the dependent
@@ -483,16 +500,16 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
         for (int ks = 0; ks < C::PKS; ++ks) {
 #pragma unroll
             for (int t = 0; t < N; ++t) {
-                double xv = xa[t][4 * ks], bv = ab[t][4 * ks];
+                TP xv = xa[t][4 * ks], bv = ab[t][4 * ks];
                 if constexpr (NORB % 2 != 0) {  // the last k-step runs past u = Norb - 1
                     const bool u_ok = 2 * ks + (kk >> 1) < NORB;
-                    xv = u_ok ? xv : 0.0;
-                    bv = u_ok ? bv : 0.0;
+                    xv = u_ok ? xv : TP(0);
+                    bv = u_ok ? bv : TP(0);
                 }
                 if ((ks & 1) && PREC != SSE_FP64)
-                    acc1[t] = OP::mma(OP::neg_if(TP(xv), pt_neg[s0 + t]), TP(bv), acc1[t]);
+                    acc1[t] = OP::mma(OP::neg_if(xv, pt_neg[s0 + t]), bv, acc1[t]);
                 else
-                    acc0[t] = OP::mma(OP::neg_if(TP(xv), pt_neg[s0 + t]), TP(bv), acc0[t]);
+                    acc0[t] = OP::mma(OP::neg_if(xv, pt_neg[s0 + t]), bv, acc0[t]);
             }
         }
 #pragma unroll
@@ -501,9 +518,12 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
             if constexpr (PREC != SSE_FP64) acc += acc1[t];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                if constexpr (F16)
-                    P[pt_out[s0 + t][v]] = split_b(acc[v]);
-                else
+                if constexpr (F16) {
+                    unsigned* q = reinterpret_cast<unsigned*>(P + pt_out[s0 + t][v]);
+                    const unsigned w = split_b_word(acc[v]);
+                    q[0] = w;
+                    q[1] = w;
+                } else
                     P[pt_out[s0 + t][v]] = T(acc[v]);
             }
         }
@@ -511,8 +531,8 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     auto p_tiles = [&](int g) {
         if (g >= niter) return;
         const int np = (g % C::NCHUNK) % C::NP;
-        const double* Xb = sX + (g & 1) * C::XB;
-        const double* Ab = sA + np * C::PSTR;
+        const TP* Xb = sX + (g & 1) * C::XB;
+        const TP* Ab = sAp + np * C::PSTR;
         T* P = sP + (g & 1) * C::PBS;
         // tiles in pairs, a last single one if the wave's count is odd
 #pragma unroll
