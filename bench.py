@@ -84,8 +84,11 @@ def cpu_baseline(d, G, D, dH, nbr, outputs, target_s, f_block, seed=7):
         aa = rng.choice(atoms, size=n)
         return [(int(k), int(e), int(a)) for k, e, a in zip(ks, es, aa)]
 
-    # calibrate, then run a sample sized to target_s
-    cal = pts_for(16)
+    # calibrate on enough blocks to keep every host thread busy (a short
+    # calibration overestimates the per-block time), then run a sample sized
+    # to target_s
+    oracle.sse_points(sub, Gs, Ds, Hs, nbs, [(k, e, remap[a]) for k, e, a in pts_for(32)])  # warm-up
+    cal = pts_for(512)
     t0 = time.perf_counter()
     oracle.sse_points(sub, Gs, Ds, Hs, nbs, [(k, e, remap[a]) for k, e, a in cal])
     per = (time.perf_counter() - t0) / len(cal)
