@@ -41,8 +41,10 @@ def _open(path):
     lib.oracle_sse_backward.argtypes = [P, P, P, P, P, ctypes.c_double, ctypes.c_double, P, P, P, P]
     lib.oracle_num_threads.argtypes = []
     lib.oracle_combine_d.argtypes = [P, P, P, P]
+    lib.oracle_pse_points.argtypes = [P, P, P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_int64, P, P]
+    lib.oracle_pse_forward.argtypes = [P, P, P, P, P, ctypes.c_double, ctypes.c_double, P]
     for f in (lib.oracle_sse_points, lib.oracle_sse_forward, lib.oracle_sse_backward, lib.oracle_num_threads,
-              lib.oracle_combine_d):
+              lib.oracle_combine_d, lib.oracle_pse_points, lib.oracle_pse_forward):
         f.restype = ctypes.c_int
     return lib
 
@@ -134,6 +136,42 @@ def combine_d(dims, Dfull, nbr, lib=None) -> np.ndarray:
     return out
 
 
+def _check_pse_inputs(dims, Gs, Go, dH, nbr):
+    _check(Gs, dims.g_shape, np.complex128, "Gs")
+    _check(Go, dims.g_shape, np.complex128, "Go")
+    _check(dH, dims.dh_shape, np.complex128, "dH")
+    _check(nbr, dims.nbr_shape, np.int32, "nbr")
+
+
+def pse_forward(dims, Gs, Go, dH, nbr, beta=-1j, lib=None) -> np.ndarray:
+    """Phonon self-energy Pi [nqz, nw, na, nb, 3, 3] (Eq. 4, off-diagonal blocks):
+    Gs of the same component as Pi at the atom, Go of the opposite one at the
+    neighbour."""
+    _check_pse_inputs(dims, Gs, Go, dH, nbr)
+    out = np.zeros(dims.d_shape, dtype=np.complex128)
+    dd = _dims_array(dims)
+    b = complex(beta)
+    rc = (lib or _load()).oracle_pse_forward(_ptr(dd), _ptr(Gs), _ptr(Go), _ptr(dH), _ptr(nbr), b.real, b.imag,
+                                             _ptr(out))
+    if rc:
+        raise RuntimeError(f"oracle_pse_forward failed with status {rc}")
+    return out
+
+
+def pse_points(dims, Gs, Go, dH, nbr, pts, beta=-1j, lib=None) -> np.ndarray:
+    """Pi blocks at pts = [(q, w-1, a, n), ...] -> [npts, 3, 3]."""
+    _check_pse_inputs(dims, Gs, Go, dH, nbr)
+    p = np.ascontiguousarray(np.asarray(pts, dtype=np.int64).reshape(-1, 4))
+    out = np.zeros((p.shape[0], 3, 3), dtype=np.complex128)
+    dd = _dims_array(dims)
+    b = complex(beta)
+    rc = (lib or _load()).oracle_pse_points(_ptr(dd), _ptr(Gs), _ptr(Go), _ptr(dH), _ptr(nbr), b.real, b.imag,
+                                            p.shape[0], _ptr(p), _ptr(out))
+    if rc:
+        raise RuntimeError(f"oracle_pse_points failed with status {rc}")
+    return out
+
+
 def sse_status(dims_tuple, G, D, dH, nbr, lib=None) -> int:
     """Raw status of the forward entry point for arbitrary (possibly invalid) dims."""
     dd = np.asarray(dims_tuple, dtype=np.int64)
@@ -162,3 +200,9 @@ class Bound:
 
     def combine_d(self, *a, **k):
         return combine_d(*a, lib=self.lib, **k)
+
+    def pse_forward(self, *a, **k):
+        return pse_forward(*a, lib=self.lib, **k)
+
+    def pse_points(self, *a, **k):
+        return pse_points(*a, lib=self.lib, **k)

@@ -431,3 +431,138 @@ int oracle_combine_d(const int64_t* dims, const double* Dfull, const int32_t* nb
         }
     return 0;
 }
+
+/*
+ * Phonon scattering self-energy (Eq. 4 of the paper, "Current State of the
+ * Art"), for the Nb off-diagonal blocks (a, b = nbr[a,n]) the paper keeps,
+ * where the sum over l reduces to l = b:
+ *
+ *   Pi[q, w-1, a, n, i, j] = beta * sum_{k=0}^{Nkz-1} sum_{E: 0 <= E+w < NE}
+ *       tr( A[a,n,i]^H . Gs[(k+q) mod Nkz, E+w, a, 0] . A[a,n,j] . Go[k, E, nbr[a,n], 0] )
+ *
+ * with grad_i H_ba = A[a,n,i]^H and grad_j H_ab = A[a,n,j] (H Hermitian), Gs
+ * the electron Green's function of the same component as Pi (its block at
+ * atom a, shifted by +qz and +w) and Go the opposite component (its block at
+ * the neighbour b, unshifted); beta carries the prefactor -i and the energy
+ * quadrature weight.  Each term is formed as written: X = A_i^H . Gs,
+ * Y = X . A_j, then the trace of Y . Go.
+ *
+ * Output Pi [nqz][nw][na][nb][3][3] (the layout of D).
+ */
+
+/* out = X^H . Y   (N x N complex) */
+static void mat_mul_adj_left(int64_t N, const double* X, const double* Y, cplx* out) {
+    for (int64_t r = 0; r < N; ++r)
+        for (int64_t c = 0; c < N; ++c) {
+            cplx s = { 0.0, 0.0 };
+            for (int64_t t = 0; t < N; ++t) s = c_add(s, c_mul(c_conj(c_at(X, t * N + r)), c_at(Y, t * N + c)));
+            out[r * N + c] = s;
+        }
+}
+
+/* One 3x3 output block Pi[q, wi, a, n] (wi = w - 1), written to out as 9 complex. */
+static void pi_block(const odims* d, const double* Gs, const double* Go, const double* A, const int32_t* nbr,
+                     cplx beta, int64_t q, int64_t wi, int64_t a, int64_t n, cplx* X, cplx* Y, double* out) {
+    const int64_t N = d->norb, w = wi + 1;
+    const int64_t b = nbr[a * d->nb + n];
+    cplx acc[9];
+    for (int x = 0; x < 9; ++x) { acc[x].re = 0.0; acc[x].im = 0.0; }
+    for (int64_t k = 0; k < d->nkz; ++k) {
+        const int64_t ks = (k + q) % d->nkz;
+        for (int64_t e = 0; e < d->ne; ++e) {
+            const int64_t es = e + w;
+            if (es >= d->ne) continue;
+            const double* Gsa = Gs + 2 * off_G(d, ks, es, a);
+            const double* Gob = Go + 2 * off_G(d, k, e, b);
+            for (int i = 0; i < 3; ++i) {
+                mat_mul_adj_left(N, A + 2 * off_A(d, a, n, i), Gsa, X);
+                for (int j = 0; j < 3; ++j) {
+                    const double* Aj = A + 2 * off_A(d, a, n, j);
+                    for (int64_t r = 0; r < N; ++r)
+                        for (int64_t c = 0; c < N; ++c) {
+                            cplx s = { 0.0, 0.0 };
+                            for (int64_t t = 0; t < N; ++t) s = c_add(s, c_mul(X[r * N + t], c_at(Aj, t * N + c)));
+                            Y[r * N + c] = s;
+                        }
+                    cplx tr = { 0.0, 0.0 };
+                    for (int64_t r = 0; r < N; ++r)
+                        for (int64_t u = 0; u < N; ++u) tr = c_add(tr, c_mul(Y[r * N + u], c_at(Gob, u * N + r)));
+                    acc[i * 3 + j] = c_add(acc[i * 3 + j], tr);
+                }
+            }
+        }
+    }
+    for (int x = 0; x < 9; ++x) {
+        const cplx v = c_mul(beta, acc[x]);
+        out[2 * x] = v.re;
+        out[2 * x + 1] = v.im;
+    }
+}
+
+/* Pi at a list of output blocks pts[p] = (q, w-1, a, n); out is [npts][3][3]. */
+int oracle_pse_points(const int64_t* dims, const double* Gs, const double* Go, const double* A,
+                      const int32_t* nbr, double beta_re, double beta_im, int64_t npts, const int64_t* pts,
+                      double* out) {
+    odims d;
+    int rc = read_dims(dims, &d);
+    if (rc) return rc;
+    if (!Gs || !Go || !A || !nbr || (npts > 0 && (!pts || !out))) return 1;
+    if ((rc = check_nbr(&d, nbr))) return rc;
+    for (int64_t p = 0; p < npts; ++p)
+        if (pts[4 * p] < 0 || pts[4 * p] >= d.nqz || pts[4 * p + 1] < 0 || pts[4 * p + 1] >= d.nw ||
+            pts[4 * p + 2] < 0 || pts[4 * p + 2] >= d.na || pts[4 * p + 3] < 0 || pts[4 * p + 3] >= d.nb)
+            return 2;
+    const cplx beta = { beta_re, beta_im };
+    const int64_t NN = d.norb * d.norb;
+    int fail = 0;
+#pragma omp parallel
+    {
+        cplx* X = (cplx*)malloc(sizeof(cplx) * NN);
+        cplx* Y = (cplx*)malloc(sizeof(cplx) * NN);
+        if (!X || !Y) {
+#pragma omp atomic write
+            fail = 1;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t p = 0; p < npts; ++p)
+                pi_block(&d, Gs, Go, A, nbr, beta, pts[4 * p], pts[4 * p + 1], pts[4 * p + 2], pts[4 * p + 3], X, Y,
+                         out + 18 * p);
+        }
+        free(X);
+        free(Y);
+    }
+    return fail ? 7 : 0;
+}
+
+/* Full Pi [nqz][nw][na][nb][3][3]. */
+int oracle_pse_forward(const int64_t* dims, const double* Gs, const double* Go, const double* A,
+                       const int32_t* nbr, double beta_re, double beta_im, double* Pi) {
+    odims d;
+    int rc = read_dims(dims, &d);
+    if (rc) return rc;
+    if (!Gs || !Go || !A || !nbr || !Pi) return 1;
+    if ((rc = check_nbr(&d, nbr))) return rc;
+    const cplx beta = { beta_re, beta_im };
+    const int64_t NN = d.norb * d.norb;
+    const int64_t nblk = d.nqz * d.nw * d.na * d.nb;
+    int fail = 0;
+#pragma omp parallel
+    {
+        cplx* X = (cplx*)malloc(sizeof(cplx) * NN);
+        cplx* Y = (cplx*)malloc(sizeof(cplx) * NN);
+        if (!X || !Y) {
+#pragma omp atomic write
+            fail = 1;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t x = 0; x < nblk; ++x) {
+                const int64_t n = x % d.nb, a = (x / d.nb) % d.na, wi = (x / (d.nb * d.na)) % d.nw,
+                              q = x / (d.nb * d.na * d.nw);
+                pi_block(&d, Gs, Go, A, nbr, beta, q, wi, a, n, X, Y, Pi + 18 * x);
+            }
+        }
+        free(X);
+        free(Y);
+    }
+    return fail ? 7 : 0;
+}

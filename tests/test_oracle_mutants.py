@@ -67,3 +67,55 @@ def test_mutant_is_caught(tmp_path, name):
     oracle.build(src=str(path), out=so)
     failed = _pin_checks(oracle.Bound(so))
     assert failed, f"mutant {name} passed every pin"
+
+
+# Slips in the phonon self-energy (Eq. 4) part of the oracle, checked against its own pins.
+import test_oracle_pse_pins as pse_pins
+
+PSE_MUTANTS = {
+    "pse_k_minus_q": ("const int64_t ks = (k + q) % d->nkz;", "const int64_t ks = ((k - q) % d->nkz + d->nkz) % d->nkz;"),
+    "pse_freq_off_by_one": ("const int64_t es = e + w;", "const int64_t es = e + w - 1;"),
+    "pse_transpose_not_adjoint": ("c_conj(c_at(X, t * N + r))", "c_at(X, t * N + r)"),
+    "pse_go_at_atom": ("const double* Gob = Go + 2 * off_G(d, k, e, b);", "const double* Gob = Go + 2 * off_G(d, k, e, a);"),
+    "pse_same_component": ("const double* Gob = Go + 2 * off_G(d, k, e, b);", "const double* Gob = Gs + 2 * off_G(d, k, e, b);"),
+    "pse_trace_transposed": ("c_at(Gob, u * N + r)", "c_at(Gob, r * N + u)"),
+    "pse_no_beta": ("const cplx v = c_mul(beta, acc[x]);", "const cplx v = acc[x];"),
+    "pse_energy_edge": ("if (es >= d->ne) continue;", "if (es >= d->ne - 1) continue;"),
+    "pse_ij_swapped": ("acc[i * 3 + j] = c_add(acc[i * 3 + j], tr);", "acc[j * 3 + i] = c_add(acc[j * 3 + i], tr);"),
+}
+
+
+def _pse_pin_checks(lib):
+    failed = []
+    checks = [
+        ("closed_form_a", lambda: pse_pins.test_delta_inputs_closed_form_bit_exact(lib, 2, 5, 1, 3, 1, 2, 1)),
+        ("closed_form_b", lambda: pse_pins.test_delta_inputs_closed_form_bit_exact(lib, 0, 8, 2, 7, 2, 1, 2)),
+        ("dense", lambda: pse_pins.test_brute_force_dense_einsum(lib)),
+        ("correlate", lambda: pse_pins.test_textbook_reduction_to_correlate(lib)),
+        ("anti_hermitian", lambda: pse_pins.test_anti_hermitian_for_anti_hermitian_inputs(lib)),
+        ("homogeneity", lambda: pse_pins.test_linearity_and_homogeneity(lib)),
+        ("ne1_zero", lambda: pse_pins.test_single_energy_point_is_zero(lib)),
+    ]
+    for name, fn in checks:
+        try:
+            fn()
+        except AssertionError:
+            failed.append(name)
+    return failed
+
+
+def test_unmutated_oracle_passes_pse_pins():
+    assert _pse_pin_checks(oracle.Bound(oracle.LIB if os.path.exists(oracle.LIB) else oracle.build())) == []
+
+
+@pytest.mark.parametrize("name", sorted(PSE_MUTANTS))
+def test_pse_mutant_is_caught(tmp_path, name):
+    old, new = PSE_MUTANTS[name]
+    src = open(oracle.SRC).read()
+    assert src.count(old) == 1, f"mutation site for {name} not unique"
+    path = tmp_path / f"mut_{name}.c"
+    path.write_text(src.replace(old, new))
+    so = str(tmp_path / f"libmut_{name}.so")
+    oracle.build(src=str(path), out=so)
+    failed = _pse_pin_checks(oracle.Bound(so))
+    assert failed, f"mutant {name} passed every pin"
