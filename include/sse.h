@@ -168,6 +168,28 @@ int sse_combine_d(const sse_dims* dims, const double* Dfull, const int32_t* nbr,
                   size_t workspace_bytes, void* stream);
 
 /*
+ * Phonon scattering self-energy (Eq. 4, Sec. "Current State of the Art") for
+ * the NB off-diagonal blocks per atom that the paper keeps, (a, b = nbr[a,n]),
+ * where the sum over l reduces to l = b:
+ *
+ *   Pi[q, w-1, a, n, i, j] = beta * sum_{k=0}^{Nkz-1} sum_{E : 0 <= E+w < NE}
+ *       tr( dH[a,n,i]^H . Gs[(k+q) mod Nkz, E+w, a, 0] . dH[a,n,j] . Go[k, E, nbr[a,n], 0] )
+ *
+ * grad_i H_ba = dH[a,n,i]^H and grad_j H_ab = dH[a,n,j] (H is Hermitian).  Gs
+ * is the electron Green's function of the same component as Pi (G< for Pi<),
+ * Go the opposite one (G> for Pi<), both laid out like G (slot 0 read).  beta
+ * carries the prefactor -i of Eq. 4 and the energy quadrature weight.  The
+ * phonon frequency w sits on the electron energy grid, w = 1..Nw; the momentum
+ * grids coincide (Nqz = Nkz) and kz + qz wraps around.
+ * Output Pi [nqz][nw][na][nb][3][3] complex (the layout of D), fully
+ * overwritten.  fp64 throughout; no workspace.  Gs and Go may alias.
+ * Errors as for sse_forward (SSE_ERR_DIMS also when no kernel covers the
+ * shape: norb^2 > 640 or nqz * nw > 512 outside the matrix-core shape).
+ */
+int sse_phonon_forward(const sse_dims* dims, const double* Gs, const double* Go, const double* dH,
+                       const int32_t* nbr, double beta_re, double beta_im, double* Pi, void* stream);
+
+/*
  * Synchronous check of a neighbour table: returns SSE_OK if every entry lies
  * in [0, na), SSE_ERR_NBR otherwise.  Needs sse_workspace_bytes(dims, 0, 0)
  * bytes of workspace, at least 4; copies one int32 back to the host and waits

@@ -170,6 +170,19 @@ int sse_combine_d(const sse_dims* dims, const double* Dfull, const int32_t* nbr,
     return ok();
 }
 
+int sse_phonon_forward(const sse_dims* dims, const double* Gs, const double* Go, const double* dH, const int32_t* nbr,
+                       double beta_re, double beta_im, double* Pi, void* stream) {
+    int rc = check_dims(dims);
+    if (rc) return rc;
+    if (!Gs || !Go || !dH || !nbr || !Pi) return fail(SSE_ERR_NULL, "a tensor pointer is NULL");
+    const sse::Dims d = sse::to_dims(*dims);
+    if (!sse::pse_mfma_specialised(d) && !sse::pse_generic_supported(d))
+        return fail(SSE_ERR_DIMS, "no phonon self-energy kernel for these dims");
+    hipError_t e = sse::launch_pse(d, Gs, Go, dH, nbr, sse::cd{beta_re, beta_im}, Pi, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "phonon forward launch");
+    return ok();
+}
+
 int sse_check_nbr(const sse_dims* dims, const int32_t* nbr, void* workspace, size_t workspace_bytes, void* stream) {
     int rc = check_dims(dims);
     if (rc) return rc;

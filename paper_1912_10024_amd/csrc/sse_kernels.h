@@ -27,6 +27,13 @@ hipError_t launch_reverse_slots(const Dims& d, const int32_t* nbr, void* ws, hip
 hipError_t launch_combine_d(const Dims& d, const double* Dfull, const int32_t* nbr, double* Dc, void* ws,
                             hipStream_t stream);
 
+// phonon self-energy (Eq. 4, off-diagonal blocks): matrix-core kernel for the shape it is
+// instantiated for, a vector-ALU kernel for every other shape that fits
+bool pse_mfma_specialised(const Dims& d);
+bool pse_generic_supported(const Dims& d);
+hipError_t launch_pse(const Dims& d, const double* Gs, const double* Go, const double* A, const int32_t* nbr, cd beta,
+                      double* Pi, hipStream_t stream);
+
 // neighbour-table range check: sets *flag (device int) to 1 if any entry is outside [0, na)
 hipError_t launch_check_nbr(const Dims& d, const int32_t* nbr, int* flag, hipStream_t stream);
 

@@ -126,6 +126,38 @@ def forward(G, D, dH, nbr, alpha=1j, precision: str = "fp64", out=None, ws=None)
     return out
 
 
+def phonon_forward(Gs, Go, dH, nbr, nqz: int, nw: int, beta=-1j, out=None) -> torch.Tensor:
+    """Pi[nqz, nw, na, nb, 3, 3] = Eq. 4 for the nb off-diagonal blocks per atom.
+
+    Gs is the electron Green's function of the same component as Pi, Go the
+    opposite one (both [nkz, ne, na, slots, norb, norb]); beta carries -i and
+    the energy quadrature weight."""
+    if Gs.dim() != 6 or dH.dim() != 5 or nbr.dim() != 2:
+        raise ValueError("expected Gs/Go[nkz,ne,na,slots,norb,norb], dH[na,nb,3,norb,norb], nbr[na,nb]")
+    nkz, ne, na, gs, norb, _ = Gs.shape
+    d = Dims(nkz=nkz, ne=ne, nqz=int(nqz), nw=int(nw), na=na, nb=nbr.shape[1], norb=norb, g_slots=gs)
+    if tuple(Go.shape) != tuple(Gs.shape) or tuple(Gs.shape) != d.g_shape:
+        raise ValueError(f"Gs and Go must both be {d.g_shape}, got {tuple(Gs.shape)} and {tuple(Go.shape)}")
+    if tuple(dH.shape) != d.dh_shape or tuple(nbr.shape) != d.nbr_shape:
+        raise ValueError(f"dH must be {d.dh_shape} and nbr {d.nbr_shape}")
+    for t, n in ((Gs, "Gs"), (Go, "Go"), (dH, "dH")):
+        _check_tensor(t, n)
+    _check_tensor(nbr, "nbr", torch.int32)
+    if out is None:
+        out = torch.empty(d.d_shape, dtype=torch.complex128, device=Gs.device)
+    else:
+        _check_tensor(out, "out")
+        if tuple(out.shape) != d.d_shape:
+            raise ValueError(f"out must be {d.d_shape}")
+    lib = _lib.load()
+    cd = _lib.SSEDims.of(d)
+    b = complex(beta)
+    rc = lib.sse_phonon_forward(ctypes.byref(cd), _ptr(Gs), _ptr(Go), _ptr(dH), _ptr(nbr), b.real, b.imag, _ptr(out),
+                                _stream(Gs.device))
+    _raise(rc, "sse_phonon_forward")
+    return out
+
+
 def backward(G, D, dH, nbr, dSigma, alpha=1j, need=(True, True, True), ws=None):
     """(dL/dG, dL/dD, dL/d dH) for dSigma = dL/dSigma (PyTorch complex-gradient convention)."""
     d = dims_of(G, D, dH, nbr)

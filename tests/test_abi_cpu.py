@@ -97,3 +97,17 @@ def test_backward_and_check_reject_bad_input(lib):
     good = _lib.SSEDims.of(CONFIGS["tiny"])
     assert lib.sse_check_nbr(ctypes.byref(good), None, ctypes.c_void_p(1), 256, None) == _lib.SSE_ERR_NULL
     assert lib.sse_check_nbr(ctypes.byref(good), ctypes.c_void_p(1), None, 0, None) == _lib.SSE_ERR_WORKSPACE
+
+
+def test_phonon_forward_rejects_bad_input(lib):
+    P = ctypes.c_void_p
+    bad = _lib.SSEDims(3, 4, 2, 2, 3, 2, 2, 1)  # nqz != nkz
+    assert lib.sse_phonon_forward(ctypes.byref(bad), P(1), P(1), P(1), P(1), 0.0, -1.0, P(1), None) == _lib.SSE_ERR_DIMS
+    big = _lib.SSEDims(3, 4, 3, 200, 3, 2, 2, 1)  # nqz * nw beyond the vector-ALU kernel, not the matrix-core shape
+    assert lib.sse_phonon_forward(ctypes.byref(big), P(1), P(1), P(1), P(1), 0.0, -1.0, P(1), None) == _lib.SSE_ERR_DIMS
+    assert b"kernel" in lib.sse_last_error()
+    good = _lib.SSEDims.of(CONFIGS["tiny"])
+    for i in range(5):
+        ptrs = [P(1)] * 5
+        ptrs[i] = None
+        assert lib.sse_phonon_forward(ctypes.byref(good), *ptrs[:4], 0.0, -1.0, ptrs[4], None) == _lib.SSE_ERR_NULL
