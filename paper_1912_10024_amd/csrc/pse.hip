@@ -9,19 +9,23 @@
 // neighbour slot, and reused by all Nqz * Nw shifted Gs blocks it meets (the
 // same fission the paper applies to Eq. 3, Sec. "Dataflow Optimizations").
 //
-// pse_mfma_kernel (Norb 10, Nkz 7, Nw 10, NB 4): one workgroup of 4 waves per
+// pse_mfma_kernel (Norb 10, Nkz 7, Nw 10, NB 4): one workgroup of 8 waves per
 // atom a sweeps the source points (E outer, k inner).  Per source point:
 //   1. V[n][j] = A_j . Go[k, E, nbr[a,n]]          (fp64 VALU, LDS)
 //   2. T[n][i][j] = V[n][j] . A_i^H                 (fp64 VALU, into two LDS planes)
 //   3. C[(q,w), (n,i,j,re/im)] += sum over (s,t,re/im) of
 //        Gs[(k+q) mod Nkz, E+w, a][s][t] (re or im) * B[(s,t,re/im), (n,i,j,re/im)]
 //      on the fp64 matrix cores: M = Nkz Nw = 70 rows (5 tiles), N = 2 * 9 NB = 72
-//      columns (5 tiles), K = 2 Norb^2 = 200 (50 k-steps dealt round-robin to the
-//      waves).  B is the real embedding [[Tr, Ti], [-Ti, Tr]] of T; the A rows are
-//      read straight from Gs in global memory (one row = one Gs block, reused by
-//      the 5 column tiles).
-// After the sweep the four waves' accumulators are added in a fixed order in
-// LDS, scaled by beta and written out; every output entry is written once.
+//      columns (5 tiles), K = 2 Norb^2 = 200 (50 k-steps).  B is the real
+//      embedding [[Tr, Ti], [-Ti, Tr]] of T; the A rows are read straight from Gs
+//      in global memory (one row = one Gs block, reused by the column tiles).
+//      The waves form 4 K groups (k-steps dealt round-robin) x 2 tile groups
+//      (13 and 12 of the 25 tiles), so the two waves on a SIMD share its matrix
+//      core and each hides the other's load and barrier waits.
+// Two barriers per source point: Go is double-buffered in LDS and prefetched
+// two points ahead in registers.  After the sweep the K groups' accumulators
+// are added in a fixed order in LDS, scaled by beta and written out; every
+// output entry is written once.
 //
 // pse_generic_kernel (any other shape): one workgroup per neighbour slot, the
 // same three steps on the vector ALUs with one thread per (q, w).
@@ -37,34 +41,47 @@ __device__ const double pse_zero_block[256] = {};
 
 template <int N, int NK, int NW, int NB>
 struct PseCfg {
-    static constexpr int WAVES = 4, THREADS = 64 * WAVES;
+    static constexpr int KG = 4;                       // K groups: k-steps kg, kg + KG, ...
+    static constexpr int TG = 2;                       // tile groups
+    static constexpr int WAVES = KG * TG, THREADS = 64 * WAVES;
     static constexpr int NN = N * N;
     static constexpr int NCOLC = 9 * NB;               // complex GEMM columns (n, i, j)
     static constexpr int NT = (2 * NCOLC + 15) / 16;   // column tiles
     static constexpr int CPAD = 8 * NT;                // complex columns per T plane row, with padding
     static constexpr int MROWS = NK * NW;              // (q, w) rows
     static constexpr int MT = (MROWS + 15) / 16;       // row tiles
+    static constexpr int NTILES = MT * NT;
+    static constexpr int SL = (NTILES + 1) / 2;        // tiles (accumulator slots) of tile group 0
+    static constexpr int ML = (SL + NT - 1) / NT;      // row tiles a wave touches
     static constexpr int KSTEPS = NN / 2;              // 2 Norb^2 real K rows, 4 per k-step
-    static constexpr int KS_MAX = (KSTEPS + WAVES - 1) / WAVES;
+    static constexpr int KS_MAX = (KSTEPS + KG - 1) / KG;
     // the im plane starts 8 doubles (16 LDS banks) past a multiple of the re
     // plane size, so a 16-lane group reading 8 columns of each plane is conflict-free
     static constexpr int PLANE = NN * CPAD + 8;
     static constexpr int L_A = NB * 3 * NN * 2;        // grad H of the atom (doubles)
-    static constexpr int L_GO = NB * NN * 2;           // Go blocks of the source point
+    static constexpr int L_GO = 2 * NB * NN * 2;       // Go blocks, double-buffered
     static constexpr int L_V = NB * 3 * NN * 2;        // V = A_j Go
     static constexpr int L_T = 2 * PLANE;              // T planes (re, im)
-    static constexpr int L_RED = WAVES * NT * 256;     // reduction scratch, aliases the T planes
+    static constexpr int L_RED = KG * NT * 256;        // reduction scratch, aliases the T planes
     static constexpr int L_TR = L_T > L_RED ? L_T : L_RED;
     static constexpr size_t LDS_BYTES = sizeof(double) * (L_A + L_GO + L_V + L_TR);
-    static constexpr int GO_PER_THREAD = (NB * NN + THREADS - 1) / THREADS;
     static_assert(NN % 2 == 0, "K = 2 Norb^2 must split into k-steps of 4");
     static_assert(2 * NN <= 256, "zero block too small");
     static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
-    static_assert(NB * N * N <= 2 * THREADS, "formation tasks: at most two per thread");
+    static_assert(NB * N * N <= THREADS, "formation tasks: at most one per thread");
+    static_assert(NTILES - SL <= SL && ML <= MT, "tile groups");
 };
 
+// Tile of accumulator slot s: group 0 holds tiles 0 .. SL-1 in row-major
+// order, group 1 the rest counted from the last tile backwards, so both
+// groups run the same slot schedule with mirrored tile indices.
+template <class C>
+__device__ __forceinline__ int pse_tile_mt(int tg, int s) { return tg ? C::MT - 1 - s / C::NT : s / C::NT; }
+template <class C>
+__device__ __forceinline__ int pse_tile_nt(int tg, int s) { return tg ? C::NT - 1 - s % C::NT : s % C::NT; }
+
 template <int N, int NK, int NW, int NB>
-__global__ __launch_bounds__(256) void pse_mfma_kernel(Dims d, const double* __restrict__ Gs,
+__global__ __launch_bounds__(512) void pse_mfma_kernel(Dims d, const double* __restrict__ Gs,
                                                        const double* __restrict__ Go, const double* __restrict__ Ag,
                                                        const int32_t* __restrict__ nbr, cd beta,
                                                        double* __restrict__ Pi) {
@@ -72,10 +89,11 @@ __global__ __launch_bounds__(256) void pse_mfma_kernel(Dims d, const double* __r
     constexpr int NN = C::NN;
     extern __shared__ __align__(16) double smem[];
     double* sA = smem;           // [NB][3][N][N] complex
-    double* sGo = sA + C::L_A;   // [NB][N][N] complex
+    double* sGo = sA + C::L_A;   // [2][NB][N][N] complex
     double* sV = sGo + C::L_GO;  // [NB][3 (j)][N (t)][N (r)] complex
     double* sT = sV + C::L_V;    // re plane [NN][CPAD], im plane at +PLANE; entry (s*N + t, n*9 + i*3 + j) = T_ij[t][s]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int kg = wave % C::KG, tg = wave / C::KG;
     const int64_t a = blockIdx.x;
     const int NE = (int)d.ne;
     const int64_t NA = d.na;
@@ -90,77 +108,71 @@ __global__ __launch_bounds__(256) void pse_mfma_kernel(Dims d, const double* __r
     }
     for (int x = tid; x < C::L_TR; x += C::THREADS) sT[x] = 0.0;
 
-    // Go prefetch: this thread's complex elements x = tid + 256 u of the NB blocks
-    int64_t go_off[C::GO_PER_THREAD];
-    bool go_ok[C::GO_PER_THREAD];
-#pragma unroll
-    for (int u = 0; u < C::GO_PER_THREAD; ++u) {
-        const int x = tid + C::THREADS * u;
-        const int n = x / NN;
-        const int32_t b = x < NB * NN ? nbr[a * NB + n] : -1;
-        go_ok[u] = b >= 0 && b < NA;
-        go_off[u] = go_ok[u] ? slot * b + 2 * (x % NN) : 0;
+    // Go: thread tid < NB*NN moves complex element tid of the NB blocks
+    const bool go_lane = tid < NB * NN;
+    int64_t go_off;
+    bool go_ok;
+    {
+        const int32_t b = go_lane ? nbr[a * NB + tid / NN] : -1;
+        go_ok = b >= 0 && b < NA;
+        go_off = go_ok ? slot * b + 2 * (tid % NN) : 0;
     }
-    cd gov[C::GO_PER_THREAD];
+    cd gov;
     auto load_go = [&](int src) {
         const int E = src / NK, k = src % NK;
-        const int64_t base = k * k_step + (int64_t)E * e_step;
-#pragma unroll
-        for (int u = 0; u < C::GO_PER_THREAD; ++u) {
-            const double* p = go_ok[u] ? Go + base + go_off[u] : pse_zero_block;
-            const double2 v = *reinterpret_cast<const double2*>(p);
-            gov[u] = cd{v.x, v.y};
-        }
+        const double* p = go_ok ? Go + k * k_step + (int64_t)E * e_step + go_off : pse_zero_block;
+        const double2 v = *reinterpret_cast<const double2*>(p);
+        gov = cd{v.x, v.y};
+    };
+    auto store_go = [&](int src) {
+        if (go_lane) *reinterpret_cast<double2*>(sGo + (src & 1) * (NB * NN * 2) + 2 * tid) = make_double2(gov.re, gov.im);
     };
 
     // GEMM operand lanes.  A (16 x 4 per k-step): lane holds row j16, K index kk;
     // B (4 x 16): K index kk, column j16.  K index 4 ks + kk = (Gs element
     // s*N + t = 2 ks + kk/2, re/im = kk & 1).
     const int kk = lane >> 4, j16 = lane & 15, kc = kk & 1;
-    int a_q[C::MT], a_w[C::MT];
-    bool a_row[C::MT];
+    int a_q[C::ML], a_w[C::ML];
+    bool a_row[C::ML];
 #pragma unroll
-    for (int mt = 0; mt < C::MT; ++mt) {
+    for (int ml = 0; ml < C::ML; ++ml) {
+        const int mt = tg ? C::MT - 1 - ml : ml;
         const int r = 16 * mt + j16;
-        a_row[mt] = r < C::MROWS;
-        a_q[mt] = r / NW;
-        a_w[mt] = r % NW + 1;
+        a_row[ml] = r < C::MROWS;
+        a_q[ml] = r / NW;
+        a_w[ml] = r % NW + 1;
     }
     // B: plane (re or im) and sign of this lane's entry of [[Tr, Ti], [-Ti, Tr]]
     const double* bp[C::NT];
     long long b_neg;
     {
-        const int col = j16;   // column inside a tile; the tile adds 16 (8 complex columns)
-        const int dd = col & 1;
+        const int dd = j16 & 1;
         const int plane = (kc ^ dd) ? C::PLANE : 0;
         b_neg = (kc == 1 && dd == 0) ? (long long)0x8000000000000000ull : 0ll;
 #pragma unroll
-        for (int nt = 0; nt < C::NT; ++nt)
-            bp[nt] = sT + plane + (kk >> 1) * C::CPAD + 8 * nt + (col >> 1) + 2 * wave * C::CPAD;
+        for (int nl = 0; nl < C::NT; ++nl) {
+            const int nt = tg ? C::NT - 1 - nl : nl;
+            bp[nl] = sT + plane + (kk >> 1) * C::CPAD + 8 * nt + (j16 >> 1) + 2 * kg * C::CPAD;
+        }
     }
+    const bool last_slot = tg == 0;   // group 0 owns one tile more when NTILES is odd
 
-    pse_f64x4 acc[C::MT][C::NT];
+    pse_f64x4 acc[C::SL];
 #pragma unroll
-    for (int mt = 0; mt < C::MT; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < C::NT; ++nt) acc[mt][nt] = pse_f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int s = 0; s < C::SL; ++s) acc[s] = pse_f64x4{0.0, 0.0, 0.0, 0.0};
 
     const int nsrc = NK * NE;
     load_go(0);
+    store_go(0);
+    if (nsrc > 1) load_go(1);
+    __syncthreads();
     for (int src = 0; src < nsrc; ++src) {
         const int E = src / NK, k = src % NK;
-        __syncthreads();   // the previous source point's V and T are consumed
-#pragma unroll
-        for (int u = 0; u < C::GO_PER_THREAD; ++u) {
-            const int x = tid + C::THREADS * u;
-            if (x < NB * NN) *reinterpret_cast<double2*>(sGo + 2 * x) = make_double2(gov[u].re, gov[u].im);
-        }
-        __syncthreads();
         // 1. V[n][j][t][r] = sum_u A[n][j][t][u] Go[n][u][r], three j per task
-        for (int x = tid; x < NB * NN; x += C::THREADS) {
-            const int n = x / NN, t = (x / N) % N, r = x % N;
+        if (tid < NB * NN) {
+            const int n = tid / NN, t = (tid / N) % N, r = tid % N;
             const double* A0 = sA + 2 * ((n * 3) * NN + t * N);
-            const double* G0 = sGo + 2 * (n * NN + r);
+            const double* G0 = sGo + (src & 1) * (NB * NN * 2) + 2 * (n * NN + r);
             cd v0{0.0, 0.0}, v1{0.0, 0.0}, v2{0.0, 0.0};
 #pragma unroll
             for (int u = 0; u < N; ++u) {
@@ -174,11 +186,10 @@ __global__ __launch_bounds__(256) void pse_mfma_kernel(Dims d, const double* __r
             *reinterpret_cast<double2*>(V0 + 2 * NN) = make_double2(v1.re, v1.im);
             *reinterpret_cast<double2*>(V0 + 4 * NN) = make_double2(v2.re, v2.im);
         }
-        if (src + 1 < nsrc) load_go(src + 1);
-        __syncthreads();
+        __syncthreads();   // V complete; every wave is past the previous contraction
         // 2. T[n][i][j][t][s] = sum_r V[n][j][t][r] conj(A[n][i][s][r]), nine (i, j) per task
-        for (int x = tid; x < NB * NN; x += C::THREADS) {
-            const int n = x / NN, t = (x / N) % N, s = x % N;
+        if (tid < NB * NN) {
+            const int n = tid / NN, t = (tid / N) % N, s = tid % N;
             const double* V0 = sV + 2 * ((n * 3) * NN + t * N);
             const double* A0 = sA + 2 * ((n * 3) * NN + s * N);
             cd tv[9];
@@ -204,55 +215,61 @@ __global__ __launch_bounds__(256) void pse_mfma_kernel(Dims d, const double* __r
                 T0[C::PLANE + ij] = tv[ij].im;
             }
         }
-        // A row bases of this source point (the wave's first k-step and the lane's K index folded in)
-        const double* ap[C::MT];
+        // Go of the next source point into the free buffer, the one after that into registers
+        if (src + 1 < nsrc) store_go(src + 1);
+        if (src + 2 < nsrc) load_go(src + 2);
+        // A row bases of this source point (the wave's first k-step and the lane's K index
+        // folded in) and the first k-step's rows
+        const double* ap[C::ML];
 #pragma unroll
-        for (int mt = 0; mt < C::MT; ++mt) {
-            const int es = E + a_w[mt];
-            const bool ok = a_row[mt] && es < NE;
-            const int kq = (k + a_q[mt]) % NK;
+        for (int ml = 0; ml < C::ML; ++ml) {
+            const int es = E + a_w[ml];
+            const bool ok = a_row[ml] && es < NE;
+            const int kq = (k + a_q[ml]) % NK;
             const double* p = ok ? Gs + kq * k_step + (int64_t)es * e_step + slot * a : pse_zero_block;
-            ap[mt] = p + 4 * wave + kk;
+            ap[ml] = p + 4 * kg + kk;
         }
-        __syncthreads();
-        // 3. the contraction on the matrix cores: k-steps wave, wave + 4, ...
-        double an[C::MT];
+        double an[C::ML];
 #pragma unroll
-        for (int mt = 0; mt < C::MT; ++mt) an[mt] = ap[mt][0];
+        for (int ml = 0; ml < C::ML; ++ml) an[ml] = ap[ml][0];
+        __syncthreads();   // T complete
+        // 3. the contraction on the matrix cores: k-steps kg, kg + KG, ...
 #pragma unroll
         for (int i = 0; i < C::KS_MAX; ++i) {
-            const bool live = wave + C::WAVES * i < C::KSTEPS;
-            double ac[C::MT];
+            const bool live = kg + C::KG * i < C::KSTEPS;
+            double ac[C::ML];
 #pragma unroll
-            for (int mt = 0; mt < C::MT; ++mt) ac[mt] = an[mt];
-            if (i + 1 < C::KS_MAX && wave + C::WAVES * (i + 1) < C::KSTEPS) {
+            for (int ml = 0; ml < C::ML; ++ml) ac[ml] = an[ml];
+            if (i + 1 < C::KS_MAX && kg + C::KG * (i + 1) < C::KSTEPS) {
 #pragma unroll
-                for (int mt = 0; mt < C::MT; ++mt) an[mt] = ap[mt][4 * C::WAVES * (i + 1)];
+                for (int ml = 0; ml < C::ML; ++ml) an[ml] = ap[ml][4 * C::KG * (i + 1)];
             }
             if (live) {
                 double bv[C::NT];
 #pragma unroll
-                for (int nt = 0; nt < C::NT; ++nt)
-                    bv[nt] = __longlong_as_double(__double_as_longlong(bp[nt][2 * C::WAVES * i * C::CPAD]) ^ b_neg);
+                for (int nl = 0; nl < C::NT; ++nl)
+                    bv[nl] = __longlong_as_double(__double_as_longlong(bp[nl][2 * C::KG * i * C::CPAD]) ^ b_neg);
 #pragma unroll
-                for (int mt = 0; mt < C::MT; ++mt)
-#pragma unroll
-                    for (int nt = 0; nt < C::NT; ++nt)
-                        acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[mt], bv[nt], acc[mt][nt], 0, 0, 0);
+                for (int s = 0; s < C::SL; ++s) {
+                    if (s == C::SL - 1 && C::SL * 2 != C::NTILES && !last_slot) continue;
+                    acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[s / C::NT], bv[s % C::NT], acc[s], 0, 0, 0);
+                }
             }
         }
     }
 
-    // Sum of the four waves' partial results in wave order, scaled by beta.
+    // Sum of the K groups' partial results in K-group order, scaled by beta.
     __syncthreads();
-    double* red = sT;   // [WAVES][NT][16 rows][16 cols]
-#pragma unroll
+    double* red = sT;   // [KG][NT][16 rows][16 cols]
     for (int mt = 0; mt < C::MT; ++mt) {
 #pragma unroll
-        for (int nt = 0; nt < C::NT; ++nt)
+        for (int s = 0; s < C::SL; ++s) {
+            if (s == C::SL - 1 && C::SL * 2 != C::NTILES && !last_slot) continue;
+            if (pse_tile_mt<C>(tg, s) != mt) continue;
+            const int nt = pse_tile_nt<C>(tg, s);
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                red[(wave * C::NT + nt) * 256 + (4 * v + (lane >> 4)) * 16 + j16] = acc[mt][nt][v];
+            for (int v = 0; v < 4; ++v) red[(kg * C::NT + nt) * 256 + (4 * v + (lane >> 4)) * 16 + j16] = acc[s][v];
+        }
         __syncthreads();
         for (int x = tid; x < C::NT * 16 * 8; x += C::THREADS) {
             const int nt = x / 128, row = (x / 8) % 16, cp = x % 8;
@@ -260,8 +277,8 @@ __global__ __launch_bounds__(256) void pse_mfma_kernel(Dims d, const double* __r
             if (rg < C::MROWS && colc < C::NCOLC) {
                 double re = 0.0, im = 0.0;
 #pragma unroll
-                for (int w = 0; w < C::WAVES; ++w) {
-                    const double* p = red + (w * C::NT + nt) * 256 + row * 16 + 2 * cp;
+                for (int g = 0; g < C::KG; ++g) {
+                    const double* p = red + (g * C::NT + nt) * 256 + row * 16 + 2 * cp;
                     re += p[0];
                     im += p[1];
                 }
