@@ -8,7 +8,9 @@ before the timed region.  One step = one sse_forward call (one of
 Sigma^< / Sigma^>), i.e. every stage of the hot path over the whole input.
 
 Prints one JSON line (rank 0).  `value` is effective TFLOP/s, the paper's
-regrouped-form flop count (f_eff) divided by the time per step.
+regrouped-form flop count (f_eff) divided by the time per step.  The line
+also carries the phonon self-energy Pi (Eq. 4) on the same workload (Gs = G<,
+Go = G>), timed the same way, under "phonon".
 """
 from __future__ import annotations
 
@@ -40,6 +42,8 @@ def parse():
                    help="comma-separated operand precisions to time; the first is the headline value")
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle baseline sample")
     p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--no-phonon", action="store_true", help="skip the phonon self-energy timing")
+    p.add_argument("--only-phonon", action="store_true", help="time only the phonon self-energy (profiling runs)")
     p.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                    help="only run a plain device copy of this many GiB (scales HBM byte counters)")
     return p.parse_args()
@@ -68,9 +72,10 @@ def compact_problem(d, G, D, dH, nbr, atoms):
     return sub, np.ascontiguousarray(Gs), np.ascontiguousarray(Ds), np.ascontiguousarray(Hs), nb_s, remap
 
 
-def cpu_baseline(d, G, D, dH, nbr, outputs, target_s, f_block, seed=7):
-    """Time the CPU oracle on a bounded sample of output blocks of this workload
-    and check those blocks against every GPU form."""
+def cpu_baseline(d, G, D, dH, nbr, target_s, f_block, seed=7):
+    """Time the CPU oracle on a bounded sample of output blocks of this workload.
+    Returns the baseline record, the sampled (k, E, a) blocks and their values,
+    which every GPU form is checked against."""
     from oracle import oracle
 
     rng = np.random.default_rng(seed)
@@ -97,12 +102,6 @@ def cpu_baseline(d, G, D, dH, nbr, outputs, target_s, f_block, seed=7):
     t0 = time.perf_counter()
     ref = oracle.sse_points(sub, Gs, Ds, Hs, nbs, [(k, e, remap[a]) for k, e, a in pts])
     t = time.perf_counter() - t0
-    errs = {}
-    import torch
-    idx = torch.tensor(pts, device=G.device)
-    for form, S in outputs.items():
-        got = S[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy()
-        errs[form] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
     return {
         "value": n * f_block / t / 1e12,
         "unit": "TFLOP/s",
@@ -110,16 +109,51 @@ def cpu_baseline(d, G, D, dH, nbr, outputs, target_s, f_block, seed=7):
         "kind": "oracle",
         "sample": f"{n} output blocks Sigma[kz,E,a] of the same workload (4 seeded atoms, random kz and E), {t:.1f} s",
         "seconds": t,
-    }, errs
+    }, pts, ref
 
 
-def recorded_traffic():
-    """HBM bytes per launch of the fp64 kernel from the committed rocprofv3
-    counters, if the kernel source is unchanged since they were taken."""
+def sampled_error(S, pts, ref):
+    import torch
+
+    idx = torch.tensor(pts, device=S.device)
+    got = S[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy()
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def phonon_sample_error(d, Gs, Go, dH, nbr, P, seed=11):
+    """Relative error of sampled Pi blocks against the CPU oracle."""
+    import torch
+    from oracle import oracle
+    from paper_1912_10024_amd.inputs import Dims
+
+    rng = np.random.default_rng(seed)
+    atoms = [int(x) for x in rng.choice(d.na, size=2, replace=False)]
+    # the Pi blocks of an atom read Gs at the atom, Go at its neighbours and its grad H
+    nbr_h = nbr.cpu().numpy()
+    keep = sorted(set(atoms) | set(int(b) for a in atoms for b in nbr_h[a]))
+    remap = {a: i for i, a in enumerate(keep)}
+    idx = torch.tensor(keep, device=Gs.device)
+    sub = Dims(nkz=d.nkz, ne=d.ne, nqz=d.nqz, nw=d.nw, na=len(keep), nb=d.nb, norb=d.norb, g_slots=1)
+    Gs_h = np.ascontiguousarray(Gs[:, :, :, :1].index_select(2, idx).cpu().numpy())
+    Go_h = np.ascontiguousarray(Go[:, :, :, :1].index_select(2, idx).cpu().numpy())
+    Hs = np.ascontiguousarray(dH.index_select(0, idx).cpu().numpy())
+    nbs = np.array([[remap[int(b)] for b in nbr_h[a]] if a in atoms else [(remap[a] + 1 + t) % len(keep)
+                                                                          for t in range(d.nb)] for a in keep],
+                   dtype=np.int32)
+    pts = [(int(rng.integers(d.nqz)), int(rng.integers(d.nw)), a, int(rng.integers(d.nb))) for a in atoms for _ in range(3)]
+    ref = oracle.pse_points(sub, Gs_h, Go_h, Hs, nbs, [(q, w, remap[a], n) for q, w, a, n in pts])
+    pidx = torch.tensor(pts, device=P.device)
+    got = P[pidx[:, 0], pidx[:, 1], pidx[:, 2], pidx[:, 3]].cpu().numpy()
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def recorded_traffic(record="fwd_mfma_device_traffic.txt", source="fwd_mfma.hip"):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counters,
+    if the kernel source is unchanged since they were taken."""
     import hashlib
 
-    rec = os.path.join(ROOT, "profiles", "fwd_mfma_device_traffic.txt")
-    src = os.path.join(ROOT, "paper_1912_10024_amd", "csrc", "fwd_mfma.hip")
+    rec = os.path.join(ROOT, "profiles", record)
+    src = os.path.join(ROOT, "paper_1912_10024_amd", "csrc", source)
     if not os.path.exists(rec):
         return None
     kv = dict(l.strip().split("=", 1) for l in open(rec) if "=" in l and not l.startswith("#"))
@@ -146,6 +180,57 @@ def time_form(sse, G, D, dH, nbr, S, ws, form, steps, warmup, dev):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return wall, [a.elapsed_time(b) for a, b in ev]
+
+
+def time_phonon(sse, Gs, Go, dH, nbr, d, P, steps, warmup, dev):
+    import torch
+
+    for _ in range(warmup):
+        sse.phonon_forward(Gs, Go, dH, nbr, d.nqz, d.nw, out=P)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for s in range(steps):
+        ev[s][0].record(stream)
+        sse.phonon_forward(Gs, Go, dH, nbr, d.nqz, d.nw, out=P)
+        ev[s][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, [a.elapsed_time(b) for a, b in ev]
+
+
+def phonon_record(args, sse, flops, d, G, dH, nbr, dev):
+    """Time Pi< = Eq. 4 with Gs = G<, Go = G> on the same workload."""
+    import torch
+    from paper_1912_10024_amd.inputs import CONFIG_INDEX, generate_device
+
+    Go = generate_device(d, CONFIG_INDEX[args.config], device=dev, which=("G>",))["G>"]
+    P = torch.empty(d.d_shape, dtype=torch.complex128, device=dev)
+    wall, kern_ms = time_phonon(sse, G, Go, dH, nbr, d, P, args.steps, args.warmup, dev)
+    ms = float(np.mean(kern_ms))
+    useful = flops.pse_flops(d)
+    rec = {
+        "workload": f"electron-phonon SSE Pi^< forward ({args.config}), Gs = G<, Go = G>",
+        "value": round(useful / (ms * 1e-3) / 1e12, 3),
+        "unit": "TFLOP/s",
+        "kernel_ms": round(ms, 3),
+        "kernel_ms_all": [round(x, 3) for x in kern_ms],
+        "ms_per_step": round(wall * 1e3 / args.steps, 3),
+        "roofline": {"bound": "mfma", "achieved": round(useful / (ms * 1e-3) / 1e12, 3),
+                     "peak": FP64_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
+                     "frac": round(useful / (ms * 1e-3) / FP64_MFMA_PEAK, 4),
+                     "traffic": (recorded_traffic("pse_mfma_device_traffic.txt", "pse.hip")
+                                 if args.config == "device" else None),
+                     "flops_per_launch": useful,
+                     "what": "useful fp64 flops: the trace contraction on the matrix cores plus T = gradH.Go.gradH^H "
+                             "on the vector ALUs (same fp64 peak)"},
+    }
+    if not args.no_cpu:
+        rec["rel_err_vs_oracle_sampled"] = phonon_sample_error(d, G, Go, dH, nbr, P)
+    del Go, P
+    torch.cuda.empty_cache()
+    return rec
 
 
 def main():
@@ -179,11 +264,25 @@ def main():
     t_gen = time.perf_counter() - t_gen
 
     f_eff = flops.f_eff(d)
+    if args.only_phonon:
+        rec = phonon_record(args, sse, flops, d, G, dH, nbr, dev)
+        print(json.dumps({"metric": "phonon SSE useful TFLOP/s (Pi, one component)", "value": rec["value"],
+                          "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": rec["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+                          "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+                          "config": {"workload": rec["workload"], "nkz": d.nkz, "ne": d.ne, "nqz": d.nqz,
+                                     "nw": d.nw, "na": d.na, "nb": d.nb, "norb": d.norb, "g_slots": d.g_slots},
+                          "roofline": rec["roofline"], "phonon": rec}), flush=True)
+        return
+    cpu = None
+    if not args.no_cpu:
+        f_block = f_eff / (d.nkz * d.ne * d.na)
+        cpu, cpu_pts, cpu_ref = cpu_baseline(d, G, D, dH, nbr, args.cpu_seconds, f_block)
     gemm = flops.pd_mfma_flops(d)
     peaks = {"fp64": FP64_MFMA_PEAK, "fp32": FP32_MFMA_PEAK, "fp16x2": FP16_MFMA_PEAK}
     # fp16x2: the four hi/lo partial products of the P.D GEMM on the fp16 matrix cores
     mfma_flops = {"fp64": gemm, "fp32": gemm, "fp16x2": 4 * flops.pd_gemm_flops(d)}
-    outputs, res = {}, {}
+    res = {}
     for form in forms:
         S = torch.empty(d.sigma_shape, dtype=torch.complex128, device=dev)
         ws = sse.workspace(d, form, device=dev)
@@ -201,7 +300,10 @@ def main():
                          "what": (f"useful {form} matrix-core flops: P.D GEMM + P = X.gradH^H products"
                                   if form != "fp16x2" else "fp16 matrix-core flops of the P.D GEMM (4 hi/lo products)")},
         }
-        outputs[form] = S
+        if cpu is not None:
+            res[form]["err"] = sampled_error(S, cpu_pts, cpu_ref)
+        del S, ws
+        torch.cuda.empty_cache()
     head = forms[0]
     if head == "fp64" and args.config == "device":
         res[head]["roofline"]["traffic"] = recorded_traffic()
@@ -231,12 +333,12 @@ def main():
                       "speedup_vs_" + head: round(res[head]["kernel_ms"] / r["kernel_ms"], 3)}
                   for f, r in res.items()},
     }
-    if not args.no_cpu:
-        f_block = f_eff / (d.nkz * d.ne * d.na)
-        cpu, errs = cpu_baseline(d, G, D, dH, nbr, outputs, args.cpu_seconds, f_block)
+    if cpu is not None:
         line["cpu_baseline"] = cpu
-        for f, e in errs.items():
-            line["forms"][f]["rel_err_vs_oracle_sampled"] = e
+        for f, r in res.items():
+            line["forms"][f]["rel_err_vs_oracle_sampled"] = r["err"]
+    if not args.no_phonon:
+        line["phonon"] = phonon_record(args, sse, flops, d, G, dH, nbr, dev)
     print(json.dumps(line), flush=True)
 
 

@@ -73,3 +73,21 @@ def min_bytes(d) -> float:
     dd = d.nqz * d.nw * d.na * d.nb * 9 * 16
     dh = d.na * d.nb * N3D * blk
     return float(g + sig + dd + dh + d.na * d.nb * 4)
+
+
+def pse_contraction_flops(d) -> float:
+    """Real flops of the phonon self-energy contraction (Eq. 4): per valid
+    (q, w, k, E, a, n), E + w < NE, the nine traces sum_{s,t} Gs[s][t] T_ij[t][s],
+    9 Norb^2 complex MACs at 8 flops each."""
+    valid = d.nkz * d.nqz * sum(max(d.ne - w, 0) for w in range(1, d.nw + 1))
+    return 8.0 * 9 * d.norb ** 2 * d.na * d.nb * valid
+
+
+def pse_formation_flops(d) -> float:
+    """Real flops of T_ij = grad_j H . Go . grad_i H^H: 3 + 9 products per (k, E, a, n)."""
+    return 8.0 * d.norb ** 3 * 12 * d.nb * d.na * d.nkz * d.ne
+
+
+def pse_flops(d) -> float:
+    """Useful fp64 flops of one phonon self-energy call (one of Pi< / Pi>)."""
+    return pse_contraction_flops(d) + pse_formation_flops(d)

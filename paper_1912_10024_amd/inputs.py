@@ -190,7 +190,8 @@ def generate_device(dims: Dims, config_index: int, device="cuda", which=("nbr", 
 
     ss = seed_streams(config_index)
     out = {}
-    for idx, name in enumerate(which):
+    for name in which:
+        idx = STREAMS.index(name)
         if name == "nbr":
             rng = np.random.default_rng(ss["nbr"])
             out[name] = torch.from_numpy(make_nbr(rng, dims.na, dims.nb)).to(device)
