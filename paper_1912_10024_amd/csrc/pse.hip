@@ -38,8 +38,11 @@ namespace sse {
 typedef double pse_f64x4 __attribute__((ext_vector_type(4)));
 
 // A zero Gs block: read by the padding rows of the GEMM and by rows whose
-// energy E + w leaves the grid, so the row loads need no branch.
-__device__ const double pse_zero_block[256] = {};
+// energy E + w leaves the grid, so the row loads need no branch.  It is never
+// written; it is not declared const so that it shares the global address space
+// with the input tensors and the selected pointer stays a global one (a flat
+// load would also count against the LDS wait counter).
+__device__ double pse_zero_block[256] = {};
 
 template <int N, int NK, int NW, int NB>
 struct PseCfg {
@@ -80,6 +83,7 @@ struct PseCfg {
     static_assert(NTILES - SL <= SL && ML <= MT, "tile groups");
     static_assert((NN - 1) * CPAD + 8 * NT - 1 < PLANE && PLANE % 16 == 8, "plane layout");
     static_assert(NN * 2 <= 3 * N * VROW * 2, "the Go block fits in the V block it precedes");
+    static_assert(N % 2 == 0 && N * (N / 2) <= 64, "formation lanes: (t, pair of r or s) per lane");
 };
 
 // Tile of accumulator slot s: group 0 holds tiles 0 .. SL-1 in row-major
@@ -145,6 +149,9 @@ __global__ __launch_bounds__(64 * (8 + NB)) void pse_mfma_kernel(
     if (wave >= C::MWAVES) {
         // ---------------- formation wave of neighbour slot n: T[n] of every source point
         const int n = wave - C::MWAVES;
+        // T of the next source point must be ready by the barrier that ends the
+        // matrix-core waves' current one: the formation wave's instructions go first
+        __builtin_amdgcn_s_setprio(2);
         const int32_t b = nbr[a * NB + n];
         const bool b_ok = b >= 0 && b < NA;
         const int64_t go_base = b_ok ? slot * b : 0;
@@ -171,67 +178,77 @@ __global__ __launch_bounds__(64 * (8 + NB)) void pse_mfma_kernel(
             if (src + 1 < nsrc) load_go(src + 1);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            // V[j][t][r] = sum_u A[j][t][u] Go[u][r], three j per task (t, r), kept in
-            // registers until every lane has read Go
-            constexpr int VR = (NN + 63) / 64;
-            cd vres[VR][3];
+            // V[j][t][r] = sum_u A[j][t][u] Go[u][r]; a lane owns (t, r0 = rp, r1 = rp + N/2)
+            // for the three j, kept in registers until every lane has read Go
+            constexpr int RH = N / 2;
+            const bool f_lane = lane < N * RH;
+            const int ft = f_lane ? lane / RH : 0, fp = lane % RH;
+            cd vres[2][3];
+            {
+                const double* A0 = myA + 2 * ft * N;
 #pragma unroll
-            for (int rd = 0; rd < VR; ++rd) {
-                const int x = lane + 64 * rd;
-                const int t = (x < NN ? x : 0) / N, r = x % N;
-                const double* A0 = myA + 2 * t * N;
-                cd v0{0.0, 0.0}, v1{0.0, 0.0}, v2{0.0, 0.0};
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) vres[h][j] = cd{0.0, 0.0};
 #pragma unroll 2
                 for (int u = 0; u < N; ++u) {
-                    const cd g{myGo[2 * (u * N + r)], myGo[2 * (u * N + r) + 1]};
-                    cfma(v0, cd{A0[2 * u], A0[2 * u + 1]}, g);
-                    cfma(v1, cd{A0[2 * (NN + u)], A0[2 * (NN + u) + 1]}, g);
-                    cfma(v2, cd{A0[2 * (2 * NN + u)], A0[2 * (2 * NN + u) + 1]}, g);
+                    const cd g0{myGo[2 * (u * N + fp)], myGo[2 * (u * N + fp) + 1]};
+                    const cd g1{myGo[2 * (u * N + fp + RH)], myGo[2 * (u * N + fp + RH) + 1]};
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        const cd av{A0[2 * (j * NN + u)], A0[2 * (j * NN + u) + 1]};
+                        cfma(vres[0][j], av, g0);
+                        cfma(vres[1][j], av, g1);
+                    }
                 }
-                vres[rd][0] = v0;
-                vres[rd][1] = v1;
-                vres[rd][2] = v2;
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
+            if (f_lane) {
 #pragma unroll
-            for (int rd = 0; rd < VR; ++rd) {
-                const int x = lane + 64 * rd;
-                if (x < NN) {
-                    double* V0 = myV + 2 * ((x / N) * C::VROW + x % N);
+                for (int h = 0; h < 2; ++h) {
+                    double* V0 = myV + 2 * (ft * C::VROW + fp + h * RH);
 #pragma unroll
                     for (int j = 0; j < 3; ++j)
-                        *reinterpret_cast<double2*>(V0 + 2 * j * N * C::VROW) = make_double2(vres[rd][j].re, vres[rd][j].im);
+                        *reinterpret_cast<double2*>(V0 + 2 * j * N * C::VROW) = make_double2(vres[h][j].re, vres[h][j].im);
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            // T[i][j][t][s] = sum_r V[j][t][r] conj(A[i][s][r]), nine (i, j) per task kap = s*N + t
-            for (int kap = lane; kap < NN; kap += 64) {
-                const int s_ = kap / N, t = kap % N;
+            // T[i][j][t][s] = sum_r V[j][t][r] conj(A[i][s][r]); a lane owns (t, s0 = sp, s1 = sp + N/2),
+            // rows kap = s*N + t of the T planes (consecutive lanes, consecutive rows)
+            if (f_lane) {
+                const int t = lane % N, sp = lane / N;
                 const double* V0 = myV + 2 * t * C::VROW;
-                const double* A0 = myA + 2 * s_ * N;
-                cd tv[9];
+                const double* A0 = myA + 2 * sp * N;
+                cd tv[2][9];
 #pragma unroll
-                for (int ij = 0; ij < 9; ++ij) tv[ij] = cd{0.0, 0.0};
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int ij = 0; ij < 9; ++ij) tv[h][ij] = cd{0.0, 0.0};
 #pragma unroll 2
                 for (int r = 0; r < N; ++r) {
-                    cd vj[3], ai[3];
+                    cd vj[3];
 #pragma unroll
-                    for (int m = 0; m < 3; ++m) {
-                        vj[m] = cd{V0[2 * (m * N * C::VROW + r)], V0[2 * (m * N * C::VROW + r) + 1]};
-                        ai[m] = cd{A0[2 * (m * NN + r)], A0[2 * (m * NN + r) + 1]};
-                    }
+                    for (int m = 0; m < 3; ++m) vj[m] = cd{V0[2 * (m * N * C::VROW + r)], V0[2 * (m * N * C::VROW + r) + 1]};
 #pragma unroll
-                    for (int i = 0; i < 3; ++i)
+                    for (int h = 0; h < 2; ++h)
 #pragma unroll
-                        for (int j = 0; j < 3; ++j) cfma_conj(tv[i * 3 + j], vj[j], ai[i]);
+                        for (int i = 0; i < 3; ++i) {
+                            const double* Ai = A0 + 2 * (i * NN + h * RH * N + r);
+                            const cd ai{Ai[0], Ai[1]};
+#pragma unroll
+                            for (int j = 0; j < 3; ++j) cfma_conj(tv[h][i * 3 + j], vj[j], ai);
+                        }
                 }
-                double* T0 = T + kap * C::CPAD + n * 9;
 #pragma unroll
-                for (int ij = 0; ij < 9; ++ij) {
-                    T0[ij] = tv[ij].re;
-                    T0[C::PLANE + ij] = tv[ij].im;
+                for (int h = 0; h < 2; ++h) {
+                    double* T0 = T + ((sp + h * RH) * N + t) * C::CPAD + n * 9;
+#pragma unroll
+                    for (int ij = 0; ij < 9; ++ij) {
+                        T0[ij] = tv[h][ij].re;
+                        T0[C::PLANE + ij] = tv[h][ij].im;
+                    }
                 }
             }
         };
@@ -250,27 +267,20 @@ __global__ __launch_bounds__(64 * (8 + NB)) void pse_mfma_kernel(
         }
     } else {
         // ---------------- matrix-core wave: K group kg, tile group tg
-        const int kg = wave % C::KG, tg = wave / C::KG;
+        // waves w and w + KG share a SIMD; pairing tile group 0 of K group g with tile
+        // group 1 of K group g + KG/2 evens out the matrix-core work per SIMD (the
+        // K groups own 13 or 12 k-steps, the tile groups 13 or 12 tiles)
+        const int tg = wave / C::KG, kg = (wave % C::KG + tg * (C::KG / 2)) % C::KG;
         // A (16 x 4 per k-step): lane holds row j16, K index kk; B (4 x 16): K index kk,
         // column j16.  K index 4 ks + kk = (Gs element s*N + t = 2 ks + kk/2, re/im = kk & 1).
         const int kk = lane >> 4, j16 = lane & 15, kc = kk & 1;
-        int a_q[C::ML], a_w[C::ML];
-        bool a_row[C::ML];
-#pragma unroll
-        for (int ml = 0; ml < C::ML; ++ml) {
-            const int mt = tg ? C::MT - 1 - ml : ml;
-            const int r = 16 * mt + j16;
-            a_row[ml] = r < C::MROWS;
-            a_q[ml] = r / NW;
-            a_w[ml] = r % NW + 1;
-        }
         // B: plane (re or im) and sign of this lane's entry of [[Tr, Ti], [-Ti, Tr]]
         int boff[C::NT];
-        long long b_neg;
+        int b_neg;   // sign bit of the high word
         {
             const int dd = j16 & 1;
             const int plane = (kc ^ dd) ? C::PLANE : 0;
-            b_neg = (kc == 1 && dd == 0) ? (long long)0x8000000000000000ull : 0ll;
+            b_neg = (kc == 1 && dd == 0) ? (int)0x80000000u : 0;
 #pragma unroll
             for (int nl = 0; nl < C::NT; ++nl) {
                 const int nt = tg ? C::NT - 1 - nl : nl;
@@ -289,9 +299,10 @@ __global__ __launch_bounds__(64 * (8 + NB)) void pse_mfma_kernel(
             const int E = src / NK, k = src % NK;
 #pragma unroll
             for (int ml = 0; ml < C::ML; ++ml) {
-                const int es = E + a_w[ml];
-                const bool ok = a_row[ml] && es < NE;
-                const int kq = (k + a_q[ml]) % NK;
+                const int r = 16 * (tg ? C::MT - 1 - ml : ml) + j16;   // GEMM row (q, w)
+                const int es = E + r % NW + 1;
+                const bool ok = r < C::MROWS && es < NE;
+                const int kq = (k + r / NW) % NK;
                 const double* p = ok ? Gs + kq * k_step + (int64_t)es * e_step + slot * a : pse_zero_block;
                 ap[ml] = p + 4 * kg + kk;
             }
@@ -322,7 +333,10 @@ __global__ __launch_bounds__(64 * (8 + NB)) void pse_mfma_kernel(
                     double bv[C::NT];
 #pragma unroll
                     for (int nl = 0; nl < C::NT; ++nl)
-                        bv[nl] = __longlong_as_double(__double_as_longlong(Tb[boff[nl] + 2 * C::KG * i * C::CPAD]) ^ b_neg);
+                    {
+                        const double x = Tb[boff[nl] + 2 * C::KG * i * C::CPAD];
+                        bv[nl] = __hiloint2double(__double2hiint(x) ^ b_neg, __double2loint(x));
+                    }
 #pragma unroll
                     for (int s = 0; s < C::SL; ++s) {
                         if (s == C::SL - 1 && C::SL * 2 != C::NTILES && !last_slot) continue;
