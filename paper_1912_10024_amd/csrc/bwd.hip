@@ -346,6 +346,7 @@ hipError_t launch_bwd(const Dims& d, const double* G, const double* D, const dou
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
+    if (dD && pse_mfma_specialised(d)) return launch_dd_mfma(d, G, A, nbr, gS, calpha, dD, stream);
     if (dD) {
         const size_t lds = bwd_lds_dd(d);
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(bwd_dd_kernel),

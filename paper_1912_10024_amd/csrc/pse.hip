@@ -116,7 +116,14 @@ __device__ __forceinline__ void pse_sum_row_tile(const Dims& d, const double* re
     }
 }
 
-template <int N, int NK, int NW, int NB>
+// ADJ = false: Pi (Eq. 4) with Gs, Go as documented above.
+// ADJ = true: the D part of the adjoint of Eq. 3 for dL/dSigma = g,
+//   dD[q, w-1, a, n][i][j] = conj(alpha) sum_{k', E'} sum_{s = +1, -1} [0 <= E' + s w < NE]
+//                            sum_{r,c} conj((A_i G[k', E', b] A_j^H)[r][c]) g[k'+q, E'+s w, a][r][c],
+// which is the same contraction with Gs := g (no slot axis), both energy
+// branches summed into each A row, and T_ij = A_j . G^H . A_i^H (the Go block
+// is staged conjugate-transposed); beta = conj(alpha).
+template <int N, int NK, int NW, int NB, bool ADJ>
 __global__ __launch_bounds__(64 * (8 + NB)) void pse_mfma_kernel(
     Dims d, const double* __restrict__ Gs, const double* __restrict__ Go, const double* __restrict__ Ag,
     const int32_t* __restrict__ nbr, cd beta, double* __restrict__ Pi) {
@@ -136,6 +143,9 @@ __global__ __launch_bounds__(64 * (8 + NB)) void pse_mfma_kernel(
     const int64_t slot = 2 * d.gs * NN;   // doubles between atoms at one (k, E)
     const int64_t e_step = slot * NA;      // doubles between energies
     const int64_t k_step = e_step * NE;    // doubles between momenta
+    // the shifted operand: Gs (laid out like G) or, for the adjoint, g (one block per atom)
+    const int64_t rs_slot = ADJ ? 2 * NN : slot;
+    const int64_t rs_e = rs_slot * NA, rs_k = rs_e * NE;
     const int nsrc = NK * NE;
 
     for (int x = tid; x < NB * 3 * NN; x += C::THREADS) {
@@ -173,7 +183,12 @@ __global__ __launch_bounds__(64 * (8 + NB)) void pse_mfma_kernel(
 #pragma unroll
             for (int u = 0; u < C::GO_PER_LANE; ++u) {
                 const int x = lane + 64 * u;
-                if (x < NN) *reinterpret_cast<double2*>(myGo + 2 * x) = make_double2(gv[u].re, gv[u].im);
+                if (x < NN) {
+                    if constexpr (ADJ)   // G^H: element (r, c) of G goes to (c, r), conjugated
+                        *reinterpret_cast<double2*>(myGo + 2 * ((x % N) * N + x / N)) = make_double2(gv[u].re, -gv[u].im);
+                    else
+                        *reinterpret_cast<double2*>(myGo + 2 * x) = make_double2(gv[u].re, gv[u].im);
+                }
             }
             if (src + 1 < nsrc) load_go(src + 1);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -293,24 +308,31 @@ __global__ __launch_bounds__(64 * (8 + NB)) void pse_mfma_kernel(
 #pragma unroll
         for (int s = 0; s < C::SL; ++s) acc[s] = pse_f64x4{0.0, 0.0, 0.0, 0.0};
 
-        // A rows of a source point: the wave's first k-step and the lane's K index folded in
+        // A rows of a source point: the wave's first k-step and the lane's K index folded
+        // in; the adjoint adds the row of the lower energy branch (ap2)
         const double* ap[C::ML];
+        const double* ap2[C::ML];
         auto a_rows = [&](int src) {
             const int E = src / NK, k = src % NK;
 #pragma unroll
             for (int ml = 0; ml < C::ML; ++ml) {
                 const int r = 16 * (tg ? C::MT - 1 - ml : ml) + j16;   // GEMM row (q, w)
-                const int es = E + r % NW + 1;
+                const int w = r % NW + 1, es = E + w;
                 const bool ok = r < C::MROWS && es < NE;
                 const int kq = (k + r / NW) % NK;
-                const double* p = ok ? Gs + kq * k_step + (int64_t)es * e_step + slot * a : pse_zero_block;
-                ap[ml] = p + 4 * kg + kk;
+                const double* base = Gs + kq * rs_k + rs_slot * a;
+                ap[ml] = (ok ? base + (int64_t)es * rs_e : pse_zero_block) + 4 * kg + kk;
+                if constexpr (ADJ) {
+                    const bool ok2 = r < C::MROWS && E - w >= 0;
+                    ap2[ml] = (ok2 ? base + (int64_t)(E - w) * rs_e : pse_zero_block) + 4 * kg + kk;
+                }
             }
         };
+        auto a_load = [&](int ml, int off) { return ADJ ? ap[ml][off] + ap2[ml][off] : ap[ml][off]; };
         double an[C::ML];
         a_rows(0);
 #pragma unroll
-        for (int ml = 0; ml < C::ML; ++ml) an[ml] = ap[ml][0];
+        for (int ml = 0; ml < C::ML; ++ml) an[ml] = a_load(ml, 0);
         __syncthreads();   // T of source point 0 is formed
         for (int src = 0; src < nsrc; ++src) {
             const double* Tb = sT + (src & 1) * C::TBUF;
@@ -322,12 +344,12 @@ __global__ __launch_bounds__(64 * (8 + NB)) void pse_mfma_kernel(
                 for (int ml = 0; ml < C::ML; ++ml) ac[ml] = an[ml];
                 if (i + 1 < C::KS_MAX && kg + C::KG * (i + 1) < C::KSTEPS) {
 #pragma unroll
-                    for (int ml = 0; ml < C::ML; ++ml) an[ml] = ap[ml][4 * C::KG * (i + 1)];
+                    for (int ml = 0; ml < C::ML; ++ml) an[ml] = a_load(ml, 4 * C::KG * (i + 1));
                 } else if (src + 1 < nsrc) {
                     // last k-step of this source point: the next point's first rows
                     a_rows(src + 1);
 #pragma unroll
-                    for (int ml = 0; ml < C::ML; ++ml) an[ml] = ap[ml][0];
+                    for (int ml = 0; ml < C::ML; ++ml) an[ml] = a_load(ml, 0);
                 }
                 if (live) {
                     double bv[C::NT];
@@ -453,7 +475,7 @@ hipError_t launch_pse(const Dims& d, const double* Gs, const double* Go, const d
                       double* Pi, hipStream_t stream) {
     if (pse_mfma_specialised(d)) {
         using C = PseCfg<10, 7, 10, 4>;
-        auto kern = pse_mfma_kernel<10, 7, 10, 4>;
+        auto kern = pse_mfma_kernel<10, 7, 10, 4, false>;
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS_BYTES);
         if (e != hipSuccess) return e;
@@ -467,6 +489,17 @@ hipError_t launch_pse(const Dims& d, const double* Gs, const double* Go, const d
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(pse_generic_kernel, dim3((unsigned)(d.na * d.nb)), dim3(kPseThreads), lds, stream, d, Gs, Go, A,
                        nbr, beta, Pi);
+    return hipGetLastError();
+}
+
+hipError_t launch_dd_mfma(const Dims& d, const double* G, const double* A, const int32_t* nbr, const double* gS,
+                          cd calpha, double* dD, hipStream_t stream) {
+    using C = PseCfg<10, 7, 10, 4>;
+    auto kern = pse_mfma_kernel<10, 7, 10, 4, true>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)C::LDS_BYTES);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3((unsigned)d.na), dim3(C::THREADS), C::LDS_BYTES, stream, d, gS, G, A, nbr, calpha, dD);
     return hipGetLastError();
 }
 

@@ -33,6 +33,9 @@ bool pse_mfma_specialised(const Dims& d);
 bool pse_generic_supported(const Dims& d);
 hipError_t launch_pse(const Dims& d, const double* Gs, const double* Go, const double* A, const int32_t* nbr, cd beta,
                       double* Pi, hipStream_t stream);
+// the D gradient of the adjoint on the same matrix-core kernel (shapes with pse_mfma_specialised)
+hipError_t launch_dd_mfma(const Dims& d, const double* G, const double* A, const int32_t* nbr, const double* gS,
+                          cd calpha, double* dD, hipStream_t stream);
 
 // neighbour-table range check: sets *flag (device int) to 1 if any entry is outside [0, na)
 hipError_t launch_check_nbr(const Dims& d, const int32_t* nbr, int* flag, hipStream_t stream);

@@ -34,10 +34,13 @@ SMALL = [
     (CONFIGS["tiny"], 0),
     (Dims(nkz=7, ne=14, nqz=7, nw=10, na=7, nb=4, norb=10, g_slots=5), 1),
     (Dims(nkz=3, ne=11, nqz=3, nw=4, na=6, nb=3, norb=5, g_slots=2), 2),
+    # matrix-core dD: ragged energy tail, and fewer energies than frequencies
+    (Dims(nkz=7, ne=29, nqz=7, nw=10, na=5, nb=4, norb=10, g_slots=1), 5),
+    (Dims(nkz=7, ne=5, nqz=7, nw=10, na=5, nb=4, norb=10, g_slots=2), 6),
 ]
 
 
-@pytest.mark.parametrize("dims,seed", SMALL, ids=["tiny", "norb10", "odd_nb"])
+@pytest.mark.parametrize("dims,seed", SMALL, ids=["tiny", "norb10", "odd_nb", "ragged", "ne_lt_nw"])
 def test_backward_matches_oracle(dims, seed):
     print(f"[gpu] backward parity dims={dims.as_tuple()}", flush=True)
     inp = _rand(dims, seed)
