@@ -90,28 +90,43 @@ __global__ void zero_i32_kernel(int64_t n, int32_t* p) {
 size_t bwd_workspace_bytes(const Dims& d) { return sizeof(int32_t) * (size_t)(3 * d.na + 1 + d.na * d.nb) + 256; }
 
 // --------------------------------------------------------------- W and Y of one source point
-// Thread x < NN accumulates Y_ij[x] for all nine (i,j) from the 2*Nqz*Nw shifted g blocks.
+// A zero row read in place of g blocks outside the energy grid, so the loads of
+// a batch of frequencies can all be issued before their products (never written;
+// not const, so it shares the global address space with g).
+__device__ double bwd_zero_row[2] = {0.0, 0.0};
+
+// Thread x < NN accumulates Y_ij[x] for all nine (i,j) from the 2*Nqz*Nw shifted
+// g blocks; the loads of kBatch frequencies are in flight together.
 __device__ __forceinline__ void compute_y(const Dims& d, const double* __restrict__ gS, int64_t a, int64_t kp,
                                           int64_t ep, const cd* sDn, cd calpha, int x, cd* y) {
+    constexpr int kBatch = 5;
 #pragma unroll
     for (int ij = 0; ij < 9; ++ij) y[ij] = cd{0.0, 0.0};
+    const int64_t e_stride = d.na * d.norb * d.norb;   // complex elements between energies of g
     for (int64_t q = 0; q < d.nqz; ++q) {
         const int64_t k = (kp + q) % d.nkz;
-        for (int64_t w = 1; w <= d.nw; ++w) {
-            cd wv{0.0, 0.0};
-            if (ep + w < d.ne) {
-                const cd v = cload(gS, off_S(d, k, ep + w, a) + x);
-                wv.re += v.re;
-                wv.im += v.im;
-            }
-            if (ep - w >= 0) {
-                const cd v = cload(gS, off_S(d, k, ep - w, a) + x);
-                wv.re += v.re;
-                wv.im += v.im;
-            }
-            const cd* dq = sDn + (q * d.nw + (w - 1)) * 9;
+        const double* row = gS + 2 * (off_S(d, k, ep, a) + x);   // g[k, E', a][x]
+        for (int64_t w0 = 1; w0 <= d.nw; w0 += kBatch) {
+            cd hi[kBatch], lo[kBatch];
 #pragma unroll
-            for (int ij = 0; ij < 9; ++ij) cfma_conja(y[ij], dq[ij], wv);
+            for (int t = 0; t < kBatch; ++t) {
+                const int64_t w = w0 + t;
+                const bool in = w <= d.nw, h_ok = in && ep + w < d.ne, l_ok = in && ep - w >= 0;
+                // energy offsets clamped to 0 when out of the grid, so no pointer leaves g
+                const double* ph = h_ok ? row + 2 * (h_ok ? w : 0) * e_stride : bwd_zero_row;
+                const double* pl = l_ok ? row - 2 * (l_ok ? w : 0) * e_stride : bwd_zero_row;
+                hi[t] = cd{ph[0], ph[1]};
+                lo[t] = cd{pl[0], pl[1]};
+            }
+#pragma unroll
+            for (int t = 0; t < kBatch; ++t) {
+                const int64_t w = w0 + t;
+                if (w > d.nw) break;
+                const cd wv{hi[t].re + lo[t].re, hi[t].im + lo[t].im};
+                const cd* dq = sDn + (q * d.nw + (w - 1)) * 9;
+#pragma unroll
+                for (int ij = 0; ij < 9; ++ij) cfma_conja(y[ij], dq[ij], wv);
+            }
         }
     }
 #pragma unroll
