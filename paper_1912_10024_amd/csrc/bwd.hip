@@ -14,13 +14,15 @@
 // dG and d gradH are formed by one workgroup per neighbour atom b, which walks
 // the edges that point at b (a reverse adjacency built in the workspace, in
 // edge order), so every output element has one owner: no atomics, bitwise
-// reproducible.  dD is formed by one workgroup per edge.
+// reproducible.  dD is formed by one workgroup per edge here, or by the
+// matrix-core phonon kernel in its adjoint mode for the shape it covers.
 #include "sse_kernels.h"
 
 namespace sse {
 
 namespace {
 constexpr int kBwdThreads = 256;
+constexpr int kYHalf = kBwdThreads / 2;   // first thread of the second Y group
 }
 
 // ---------------------------------------------------------------- reverse adjacency
@@ -95,33 +97,33 @@ size_t bwd_workspace_bytes(const Dims& d) { return sizeof(int32_t) * (size_t)(3 
 // not const, so it shares the global address space with g).
 __device__ double bwd_zero_row[2] = {0.0, 0.0};
 
-// Thread x < NN accumulates Y_ij[x] for all nine (i,j) from the 2*Nqz*Nw shifted
-// g blocks; the loads of kBatch frequencies are in flight together.
+// Y_ij[x] for all nine (i,j), summed over every qz and the frequencies
+// w in [w_lo, w_hi] of the 2*Nqz*Nw shifted g blocks (both energy branches);
+// the loads of kBatch frequencies are in flight together.  conj(alpha) is
+// applied by the caller.
 __device__ __forceinline__ void compute_y(const Dims& d, const double* __restrict__ gS, int64_t a, int64_t kp,
-                                          int64_t ep, const cd* sDn, cd calpha, int x, cd* y) {
+                                          int64_t ep, const cd* sDn, int64_t w_lo, int64_t w_hi, int x, cd* y) {
     constexpr int kBatch = 5;
 #pragma unroll
     for (int ij = 0; ij < 9; ++ij) y[ij] = cd{0.0, 0.0};
-    const int64_t e_stride = d.na * d.norb * d.norb;   // complex elements between energies of g
     for (int64_t q = 0; q < d.nqz; ++q) {
         const int64_t k = (kp + q) % d.nkz;
-        const double* row = gS + 2 * (off_S(d, k, ep, a) + x);   // g[k, E', a][x]
-        for (int64_t w0 = 1; w0 <= d.nw; w0 += kBatch) {
+        for (int64_t w0 = w_lo; w0 <= w_hi; w0 += kBatch) {
             cd hi[kBatch], lo[kBatch];
 #pragma unroll
             for (int t = 0; t < kBatch; ++t) {
                 const int64_t w = w0 + t;
-                const bool in = w <= d.nw, h_ok = in && ep + w < d.ne, l_ok = in && ep - w >= 0;
-                // energy offsets clamped to 0 when out of the grid, so no pointer leaves g
-                const double* ph = h_ok ? row + 2 * (h_ok ? w : 0) * e_stride : bwd_zero_row;
-                const double* pl = l_ok ? row - 2 * (l_ok ? w : 0) * e_stride : bwd_zero_row;
+                const bool in = w <= w_hi, h_ok = in && ep + w < d.ne, l_ok = in && ep - w >= 0;
+                // energies clamped to the source energy when out of the grid, so no pointer leaves g
+                const double* ph = h_ok ? gS + 2 * (off_S(d, k, h_ok ? ep + w : ep, a) + x) : bwd_zero_row;
+                const double* pl = l_ok ? gS + 2 * (off_S(d, k, l_ok ? ep - w : ep, a) + x) : bwd_zero_row;
                 hi[t] = cd{ph[0], ph[1]};
                 lo[t] = cd{pl[0], pl[1]};
             }
 #pragma unroll
             for (int t = 0; t < kBatch; ++t) {
                 const int64_t w = w0 + t;
-                if (w > d.nw) break;
+                if (w > w_hi) break;
                 const cd wv{hi[t].re + lo[t].re, hi[t].im + lo[t].im};
                 const cd* dq = sDn + (q * d.nw + (w - 1)) * 9;
 #pragma unroll
@@ -129,8 +131,6 @@ __device__ __forceinline__ void compute_y(const Dims& d, const double* __restric
             }
         }
     }
-#pragma unroll
-    for (int ij = 0; ij < 9; ++ij) y[ij] = cmul(calpha, y[ij]);
 }
 
 // --------------------------------------------------------------- dG and d gradH
@@ -152,6 +152,7 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_dg_dh_kernel(Dims d, const do
     cd* sC = sT + 3 * NN;                   // [3][N][N]   A_j B^H
     cd* sE = sC + 3 * NN;                   // [3][N][N]   A_i B
     cd* sdA = sE + 3 * NN;                  // [3][N][N]   accumulated d gradH of the edge
+    cd* sY1 = sdA + 3 * NN;                 // [9][N][N]   second half of the (q, w) sum of Y
     const int tid = threadIdx.x;
     const int64_t b = blockIdx.x;
     if (b >= d.na) return;
@@ -181,12 +182,22 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_dg_dh_kernel(Dims d, const do
         __syncthreads();
         for (int64_t kp = 0; kp < d.nkz; ++kp)
             for (int64_t ep = 0; ep < d.ne; ++ep) {
-                if (tid < NN) {
+                // Y: threads [0, NN) sum the frequencies up to Nw/2, threads
+                // [kYHalf, kYHalf + NN) the rest; the halves are then added
+                const int yh = tid >= kYHalf ? 1 : 0;
+                for (int yx = tid - yh * kYHalf; yx < NN; yx += kYHalf) {
                     cd y[9];
-                    compute_y(d, gS, a, kp, ep, sDn, calpha, tid, y);
+                    const int64_t w_mid = d.nw / 2;
+                    compute_y(d, gS, a, kp, ep, sDn, yh ? w_mid + 1 : 1, yh ? d.nw : w_mid, yx, y);
+                    cd* dst = yh ? sY1 : sY;
 #pragma unroll
-                    for (int ij = 0; ij < 9; ++ij) sY[ij * NN + tid] = y[ij];
-                    sB[tid] = cload(G, off_G(d, kp, ep, b) + tid);
+                    for (int ij = 0; ij < 9; ++ij) dst[ij * NN + yx] = y[ij];
+                    if (!yh) sB[yx] = cload(G, off_G(d, kp, ep, b) + yx);
+                }
+                __syncthreads();
+                for (int x = tid; x < 9 * NN; x += kBwdThreads) {
+                    const cd u = sY[x], v = sY1[x];
+                    sY[x] = cmul(calpha, cd{u.re + v.re, u.im + v.im});
                 }
                 __syncthreads();
                 // T_j = sum_i A_i^H Y_ij ; C_j = A_j B^H ; E_i = A_i B
@@ -325,7 +336,7 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_dd_kernel(Dims d, const doubl
 
 static size_t bwd_lds_dg(const Dims& d) {
     const size_t NN = (size_t)(d.norb * d.norb);
-    return sizeof(cd) * ((size_t)d.nqz * d.nw * 9 + 3 * NN + 9 * NN + NN + 4 * 3 * NN);
+    return sizeof(cd) * ((size_t)d.nqz * d.nw * 9 + 3 * NN + 9 * NN + NN + 4 * 3 * NN + 9 * NN);
 }
 static size_t bwd_lds_dd(const Dims& d) {
     const size_t NN = (size_t)(d.norb * d.norb);
