@@ -593,12 +593,10 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
 #pragma unroll
         for (int nt = 0; nt < C::NT; ++nt) bv[0][nt] = Pb[16 * nt];
         bx[0] = Px[0];
+        // fp32 chunk sums: the first k-step starts from a literal zero accumulator
+        // (an inline constant of the matrix instruction, no register clearing)
         typename O::Acc part[C::NT], part_x;
-        if constexpr (PREC != SSE_FP64) {
-#pragma unroll
-            for (int nt = 0; nt < C::NT; ++nt) part[nt] = typename O::Acc{0, 0, 0, 0};
-            part_x = typename O::Acc{0, 0, 0, 0};
-        }
+        const typename O::Acc zero_acc{0, 0, 0, 0};
 #pragma unroll
         for (int ks = 0; ks < C::KS; ++ks) {
             const int cur = ks & 1, nxt = cur ^ 1;
@@ -619,9 +617,9 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
             } else {
                 if (has_own) {
 #pragma unroll
-                    for (int nt = 0; nt < C::NT; ++nt) part[nt] = O::mma(a, bv[cur][nt], part[nt]);
+                    for (int nt = 0; nt < C::NT; ++nt) part[nt] = O::mma(a, bv[cur][nt], ks == 0 ? zero_acc : part[nt]);
                 }
-                if (has_extra) part_x = O::mma(b, bx[cur], part_x);
+                if (has_extra) part_x = O::mma(b, bx[cur], ks == 0 ? zero_acc : part_x);
             }
         }
         if constexpr (F16) {
