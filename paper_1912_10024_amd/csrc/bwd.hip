@@ -152,7 +152,8 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_dg_dh_kernel(Dims d, const do
     cd* sC = sT + 3 * NN;                   // [3][N][N]   A_j B^H
     cd* sE = sC + 3 * NN;                   // [3][N][N]   A_i B
     cd* sdA = sE + 3 * NN;                  // [3][N][N]   accumulated d gradH of the edge
-    cd* sY1 = sdA + 3 * NN;                 // [9][N][N]   second half of the (q, w) sum of Y
+    cd* sY1 = sT;                           // [9][N][N]   second half of the frequency sum of Y; shares
+                                            // sT, sC, sE (9 N^2), which are written only after the merge
     const int tid = threadIdx.x;
     const int64_t b = blockIdx.x;
     if (b >= d.na) return;
@@ -336,7 +337,7 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_dd_kernel(Dims d, const doubl
 
 static size_t bwd_lds_dg(const Dims& d) {
     const size_t NN = (size_t)(d.norb * d.norb);
-    return sizeof(cd) * ((size_t)d.nqz * d.nw * 9 + 3 * NN + 9 * NN + NN + 4 * 3 * NN + 9 * NN);
+    return sizeof(cd) * ((size_t)d.nqz * d.nw * 9 + 3 * NN + 9 * NN + NN + 4 * 3 * NN);
 }
 static size_t bwd_lds_dd(const Dims& d) {
     const size_t NN = (size_t)(d.norb * d.norb);
