@@ -99,35 +99,43 @@ __device__ double bwd_zero_row[2] = {0.0, 0.0};
 
 // Y_ij[x] for all nine (i,j), summed over every qz and the frequencies
 // w in [w_lo, w_hi] of the 2*Nqz*Nw shifted g blocks (both energy branches);
-// the loads of kBatch frequencies are in flight together.  conj(alpha) is
-// applied by the caller.
+// the loads of two qz and kBatch frequencies are in flight together.
+// conj(alpha) is applied by the caller.
 __device__ __forceinline__ void compute_y(const Dims& d, const double* __restrict__ gS, int64_t a, int64_t kp,
                                           int64_t ep, const cd* sDn, int64_t w_lo, int64_t w_hi, int x, cd* y) {
-    constexpr int kBatch = 5;
+    constexpr int kBatch = 5, kQ = 2;
 #pragma unroll
     for (int ij = 0; ij < 9; ++ij) y[ij] = cd{0.0, 0.0};
-    for (int64_t q = 0; q < d.nqz; ++q) {
-        const int64_t k = (kp + q) % d.nkz;
+    for (int64_t q0 = 0; q0 < d.nqz; q0 += kQ) {
         for (int64_t w0 = w_lo; w0 <= w_hi; w0 += kBatch) {
-            cd hi[kBatch], lo[kBatch];
+            cd hi[kQ][kBatch], lo[kQ][kBatch];
 #pragma unroll
-            for (int t = 0; t < kBatch; ++t) {
-                const int64_t w = w0 + t;
-                const bool in = w <= w_hi, h_ok = in && ep + w < d.ne, l_ok = in && ep - w >= 0;
-                // energies clamped to the source energy when out of the grid, so no pointer leaves g
-                const double* ph = h_ok ? gS + 2 * (off_S(d, k, h_ok ? ep + w : ep, a) + x) : bwd_zero_row;
-                const double* pl = l_ok ? gS + 2 * (off_S(d, k, l_ok ? ep - w : ep, a) + x) : bwd_zero_row;
-                hi[t] = cd{ph[0], ph[1]};
-                lo[t] = cd{pl[0], pl[1]};
+            for (int u = 0; u < kQ; ++u) {
+                const bool q_in = q0 + u < d.nqz;
+                const int64_t k = (kp + (q_in ? q0 + u : 0)) % d.nkz;
+#pragma unroll
+                for (int t = 0; t < kBatch; ++t) {
+                    const int64_t w = w0 + t;
+                    const bool in = q_in && w <= w_hi, h_ok = in && ep + w < d.ne, l_ok = in && ep - w >= 0;
+                    // energies clamped to the source energy when out of the grid, so no pointer leaves g
+                    const double* ph = h_ok ? gS + 2 * (off_S(d, k, h_ok ? ep + w : ep, a) + x) : bwd_zero_row;
+                    const double* pl = l_ok ? gS + 2 * (off_S(d, k, l_ok ? ep - w : ep, a) + x) : bwd_zero_row;
+                    hi[u][t] = cd{ph[0], ph[1]};
+                    lo[u][t] = cd{pl[0], pl[1]};
+                }
             }
 #pragma unroll
-            for (int t = 0; t < kBatch; ++t) {
-                const int64_t w = w0 + t;
-                if (w > w_hi) break;
-                const cd wv{hi[t].re + lo[t].re, hi[t].im + lo[t].im};
-                const cd* dq = sDn + (q * d.nw + (w - 1)) * 9;
+            for (int u = 0; u < kQ; ++u) {
+                if (q0 + u >= d.nqz) break;
 #pragma unroll
-                for (int ij = 0; ij < 9; ++ij) cfma_conja(y[ij], dq[ij], wv);
+                for (int t = 0; t < kBatch; ++t) {
+                    const int64_t w = w0 + t;
+                    if (w > w_hi) break;
+                    const cd wv{hi[u][t].re + lo[u][t].re, hi[u][t].im + lo[u][t].im};
+                    const cd* dq = sDn + ((q0 + u) * d.nw + (w - 1)) * 9;
+#pragma unroll
+                    for (int ij = 0; ij < 9; ++ij) cfma_conja(y[ij], dq[ij], wv);
+                }
             }
         }
     }
