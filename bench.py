@@ -10,7 +10,8 @@ Sigma^< / Sigma^>), i.e. every stage of the hot path over the whole input.
 Prints one JSON line (rank 0).  `value` is effective TFLOP/s, the paper's
 regrouped-form flop count (f_eff) divided by the time per step.  The line
 also carries the phonon self-energy Pi (Eq. 4) on the same workload (Gs = G<,
-Go = G>), timed the same way, under "phonon".
+Go = G>), timed the same way, under "phonon", and the adjoint's three
+gradients on the mid workload under "adjoint".
 """
 from __future__ import annotations
 
@@ -43,6 +44,7 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle baseline sample")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-phonon", action="store_true", help="skip the phonon self-energy timing")
+    p.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing (mid workload)")
     p.add_argument("--only-phonon", action="store_true", help="time only the phonon self-energy (profiling runs)")
     p.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                    help="only run a plain device copy of this many GiB (scales HBM byte counters)")
@@ -233,6 +235,46 @@ def phonon_record(args, sse, flops, d, G, dH, nbr, dev):
     return rec
 
 
+def adjoint_record(args, sse, dev):
+    """All three gradients of the hand-written adjoint (dG, dD, d gradH) on the
+    mid workload, the size the differentiation form is specified on, next to
+    the forward of the same size; HIP events on the current stream."""
+    import torch
+    from paper_1912_10024_amd.inputs import CONFIGS, CONFIG_INDEX, generate_device
+
+    d = CONFIGS["mid"]
+    inp = generate_device(d, CONFIG_INDEX["mid"], device=dev, which=("nbr", "G<", "D<", "dH", "W"))
+    G, D, dH, nbr = inp["G<"], inp["D<"], inp["dH"], inp["nbr"]
+    gS = inp["W"].conj().transpose(-1, -2).contiguous()   # dL/dSigma for L = Re sum tr(W Sigma)
+    ws = sse.workspace(d, backward=True, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(fn):
+        for _ in range(max(args.warmup, 1)):
+            fn()
+        torch.cuda.synchronize()
+        out = []
+        for _ in range(max(args.steps, 1)):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            out.append(a.elapsed_time(b))
+        return out
+
+    S = torch.empty(d.sigma_shape, dtype=torch.complex128, device=dev)
+    fwd = timed(lambda: sse.forward(G, D, dH, nbr, out=S))
+    bwd = timed(lambda: sse.backward(G, D, dH, nbr, gS, ws=ws))
+    del inp, G, D, dH, nbr, gS, S, ws
+    torch.cuda.empty_cache()
+    return {"workload": "adjoint dL/dG, dL/dD, dL/d gradH of L = Re sum tr(W Sigma<) (mid: Nkz=7, NE=256, "
+                        "Nqz=7, Nw=10, Na=1024, Nb=4, Norb=10)",
+            "ms_all_gradients": round(float(np.mean(bwd)), 3), "ms_all": [round(x, 3) for x in bwd],
+            "forward_ms": round(float(np.mean(fwd)), 3),
+            "ratio_to_forward": round(float(np.mean(bwd)) / float(np.mean(fwd)), 2)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -339,6 +381,10 @@ def main():
             line["forms"][f]["rel_err_vs_oracle_sampled"] = r["err"]
     if not args.no_phonon:
         line["phonon"] = phonon_record(args, sse, flops, d, G, dH, nbr, dev)
+    if not args.no_adjoint:
+        del G, D, dH, nbr, inp
+        torch.cuda.empty_cache()
+        line["adjoint"] = adjoint_record(args, sse, dev)
     print(json.dumps(line), flush=True)
 
 
