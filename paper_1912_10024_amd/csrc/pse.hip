@@ -9,8 +9,8 @@
 // neighbour slot, and reused by all Nqz * Nw shifted Gs blocks it meets (the
 // same fission the paper applies to Eq. 3, Sec. "Dataflow Optimizations").
 //
-// pse_mfma_kernel (Norb 10, Nkz 7, Nw 10, NB 4): one workgroup of 12 waves per
-// atom a sweeps the source points (E outer, k inner).  Per source point:
+// pse_mfma_kernel (Norb 10, Nkz 7, Nw 10, NB 4 or 3): one workgroup of 8 + NB
+// waves per atom a sweeps the source points (E outer, k inner).  Per source point:
 //   1. V[n][j] = A_j . Go[k, E, nbr[a,n]]          (fp64 VALU, LDS)
 //   2. T[n][i][j] = V[n][j] . A_i^H                 (fp64 VALU, into two LDS planes)
 //      Steps 1-2 run on four formation waves (one per neighbour slot n) one
@@ -18,11 +18,11 @@
 //   3. C[(q,w), (n,i,j,re/im)] += sum over (s,t,re/im) of
 //        Gs[(k+q) mod Nkz, E+w, a][s][t] (re or im) * B[(s,t,re/im), (n,i,j,re/im)]
 //      on the fp64 matrix cores: M = Nkz Nw = 70 rows (5 tiles), N = 2 * 9 NB = 72
-//      columns (5 tiles), K = 2 Norb^2 = 200 (50 k-steps).  B is the real
+//      columns (5 tiles; 54 and 4 for NB 3), K = 2 Norb^2 = 200 (50 k-steps).  B is the real
 //      embedding [[Tr, Ti], [-Ti, Tr]] of T; the A rows are read straight from Gs
 //      in global memory (one row = one Gs block, reused by the column tiles).
 //      Eight matrix-core waves form 4 K groups (k-steps dealt round-robin) x 2
-//      tile groups (13 and 12 of the 25 tiles).
+//      tile groups (13 and 12 of the 25 tiles; 10 and 10 of 20 for NB 3).
 // Each SIMD runs two matrix-core waves and one formation wave, so one wave's
 // load, LDS and barrier waits are covered by another's work; there is one
 // barrier per source point.  After the sweep the K groups' accumulators are
@@ -464,7 +464,19 @@ static size_t pse_generic_lds(const Dims& d) {
 }
 
 bool pse_mfma_specialised(const Dims& d) {
-    return d.norb == 10 && d.nkz == 7 && d.nqz == 7 && d.nw == 10 && d.nb == 4 && d.ne < (1 << 28);
+    return d.norb == 10 && d.nkz == 7 && d.nqz == 7 && d.nw == 10 && (d.nb == 4 || d.nb == 3) && d.ne < (1 << 28);
+}
+
+template <int NB, bool ADJ>
+static hipError_t launch_pse_mfma(const Dims& d, const double* Rs, const double* Go, const double* A,
+                                  const int32_t* nbr, cd beta, double* out, hipStream_t stream) {
+    using C = PseCfg<10, 7, 10, NB>;
+    auto kern = pse_mfma_kernel<10, 7, 10, NB, ADJ>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)C::LDS_BYTES);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3((unsigned)d.na), dim3(C::THREADS), C::LDS_BYTES, stream, d, Rs, Go, A, nbr, beta, out);
+    return hipGetLastError();
 }
 
 bool pse_generic_supported(const Dims& d) {
@@ -473,16 +485,9 @@ bool pse_generic_supported(const Dims& d) {
 
 hipError_t launch_pse(const Dims& d, const double* Gs, const double* Go, const double* A, const int32_t* nbr, cd beta,
                       double* Pi, hipStream_t stream) {
-    if (pse_mfma_specialised(d)) {
-        using C = PseCfg<10, 7, 10, 4>;
-        auto kern = pse_mfma_kernel<10, 7, 10, 4, false>;
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS_BYTES);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(kern, dim3((unsigned)d.na), dim3(C::THREADS), C::LDS_BYTES, stream, d, Gs, Go, A, nbr, beta,
-                           Pi);
-        return hipGetLastError();
-    }
+    if (pse_mfma_specialised(d))
+        return d.nb == 4 ? launch_pse_mfma<4, false>(d, Gs, Go, A, nbr, beta, Pi, stream)
+                         : launch_pse_mfma<3, false>(d, Gs, Go, A, nbr, beta, Pi, stream);
     const size_t lds = pse_generic_lds(d);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(pse_generic_kernel),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -494,13 +499,8 @@ hipError_t launch_pse(const Dims& d, const double* Gs, const double* Go, const d
 
 hipError_t launch_dd_mfma(const Dims& d, const double* G, const double* A, const int32_t* nbr, const double* gS,
                           cd calpha, double* dD, hipStream_t stream) {
-    using C = PseCfg<10, 7, 10, 4>;
-    auto kern = pse_mfma_kernel<10, 7, 10, 4, true>;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)C::LDS_BYTES);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3((unsigned)d.na), dim3(C::THREADS), C::LDS_BYTES, stream, d, gS, G, A, nbr, calpha, dD);
-    return hipGetLastError();
+    return d.nb == 4 ? launch_pse_mfma<4, true>(d, gS, G, A, nbr, calpha, dD, stream)
+                     : launch_pse_mfma<3, true>(d, gS, G, A, nbr, calpha, dD, stream);
 }
 
 }  // namespace sse

@@ -37,10 +37,11 @@ SMALL = [
     # matrix-core dD: ragged energy tail, and fewer energies than frequencies
     (Dims(nkz=7, ne=29, nqz=7, nw=10, na=5, nb=4, norb=10, g_slots=1), 5),
     (Dims(nkz=7, ne=5, nqz=7, nw=10, na=5, nb=4, norb=10, g_slots=2), 6),
+    (Dims(nkz=7, ne=17, nqz=7, nw=10, na=5, nb=3, norb=10, g_slots=1), 7),   # matrix-core dD, nb 3
 ]
 
 
-@pytest.mark.parametrize("dims,seed", SMALL, ids=["tiny", "norb10", "odd_nb", "ragged", "ne_lt_nw"])
+@pytest.mark.parametrize("dims,seed", SMALL, ids=["tiny", "norb10", "odd_nb", "ragged", "ne_lt_nw", "nb3"])
 def test_backward_matches_oracle(dims, seed):
     print(f"[gpu] backward parity dims={dims.as_tuple()}", flush=True)
     inp = _rand(dims, seed)

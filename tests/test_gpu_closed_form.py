@@ -18,6 +18,7 @@ from paper_1912_10024_amd.inputs import Dims, make_nbr
 pytestmark = pytest.mark.gpu
 
 SHAPES = [Dims(nkz=7, ne=23, nqz=7, nw=10, na=6, nb=4, norb=10, g_slots=2),   # matrix-core kernels
+          Dims(nkz=7, ne=19, nqz=7, nw=10, na=6, nb=3, norb=10, g_slots=1),   # matrix-core kernels, nb 3
           Dims(nkz=3, ne=11, nqz=3, nw=4, na=6, nb=3, norb=5, g_slots=2)]     # vector-ALU kernels
 
 
@@ -25,7 +26,7 @@ def _int_blocks(rng, shape):
     return (rng.integers(-4, 5, shape) + 1j * rng.integers(-4, 5, shape)).astype(np.complex128)
 
 
-@pytest.mark.parametrize("d", SHAPES, ids=["mfma", "generic"])
+@pytest.mark.parametrize("d", SHAPES, ids=["mfma", "mfma_nb3", "generic"])
 @pytest.mark.parametrize("q0,w0,n0,i0,j0", [(0, 1, 0, 0, 0), (2, 3, 1, 2, 1)])
 def test_sigma_delta_closed_form(d, q0, w0, n0, i0, j0):
     print(f"[gpu] sigma delta dims={d.as_tuple()} q0={q0} w0={w0}", flush=True)
@@ -51,7 +52,7 @@ def test_sigma_delta_closed_form(d, q0, w0, n0, i0, j0):
     assert np.array_equal(S, want)
 
 
-@pytest.mark.parametrize("d", SHAPES, ids=["mfma", "generic"])
+@pytest.mark.parametrize("d", SHAPES, ids=["mfma", "mfma_nb3", "generic"])
 def test_phonon_delta_closed_form(d):
     print(f"[gpu] phonon delta dims={d.as_tuple()}", flush=True)
     rng = np.random.default_rng(21)

@@ -43,7 +43,7 @@ SHAPES = [
     (Dims(nkz=7, ne=13, nqz=7, nw=10, na=6, nb=4, norb=10, g_slots=2), 3),     # matrix-core kernel
     (Dims(nkz=7, ne=29, nqz=7, nw=10, na=5, nb=4, norb=10, g_slots=1), 4),     # ragged energy tail
     (Dims(nkz=7, ne=5, nqz=7, nw=10, na=5, nb=4, norb=10, g_slots=1), 5),      # ne < nw
-    (Dims(nkz=7, ne=12, nqz=7, nw=10, na=5, nb=3, norb=10, g_slots=1), 6),     # nb 3: vector-ALU kernel
+    (Dims(nkz=7, ne=12, nqz=7, nw=10, na=5, nb=3, norb=10, g_slots=1), 6),     # matrix-core kernel, nb 3
 ]
 
 
