@@ -43,8 +43,11 @@ def _open(path):
     lib.oracle_combine_d.argtypes = [P, P, P, P]
     lib.oracle_pse_points.argtypes = [P, P, P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_int64, P, P]
     lib.oracle_pse_forward.argtypes = [P, P, P, P, P, ctypes.c_double, ctypes.c_double, P]
+    lib.oracle_sse_points_signed.argtypes = [P, P, P, P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_int64, P, P]
+    lib.oracle_sse_forward_signed.argtypes = [P, P, P, P, P, P, ctypes.c_double, ctypes.c_double, P]
     for f in (lib.oracle_sse_points, lib.oracle_sse_forward, lib.oracle_sse_backward, lib.oracle_num_threads,
-              lib.oracle_combine_d, lib.oracle_pse_points, lib.oracle_pse_forward):
+              lib.oracle_combine_d, lib.oracle_pse_points, lib.oracle_pse_forward, lib.oracle_sse_points_signed,
+              lib.oracle_sse_forward_signed):
         f.restype = ctypes.c_int
     return lib
 
@@ -104,6 +107,35 @@ def sse_points(dims, G, D, dH, nbr, pts, alpha=1j, lib=None) -> np.ndarray:
                                    float(np.real(alpha)), float(np.imag(alpha)), pts.shape[0], _ptr(pts), _ptr(out))
     if rc:
         raise RuntimeError(f"oracle_sse_points failed with status {rc}")
+    return out
+
+
+def sse_forward_signed(dims, G, Dp, Dm, dH, nbr, alpha=1j, lib=None) -> np.ndarray:
+    """Full Sigma of Eq. 3 over signed frequencies: terms with G at E - w read
+    Dp (coefficient at +w), terms with G at E + w read Dm (coefficient at -w)."""
+    _check_inputs(dims, G, Dp, dH, nbr)
+    _check(Dm, dims.d_shape, np.complex128, "Dm")
+    out = np.zeros(dims.sigma_shape, dtype=np.complex128)
+    dd = _dims_array(dims)
+    rc = (lib or _load()).oracle_sse_forward_signed(_ptr(dd), _ptr(G), _ptr(Dp), _ptr(Dm), _ptr(dH), _ptr(nbr),
+                                                    float(np.real(alpha)), float(np.imag(alpha)), _ptr(out))
+    if rc:
+        raise RuntimeError(f"oracle_sse_forward_signed failed with status {rc}")
+    return out
+
+
+def sse_points_signed(dims, G, Dp, Dm, dH, nbr, pts, alpha=1j, lib=None) -> np.ndarray:
+    """Blocks of sse_forward_signed at output points pts[p] = (k, e, a)."""
+    _check_inputs(dims, G, Dp, dH, nbr)
+    _check(Dm, dims.d_shape, np.complex128, "Dm")
+    pts = np.ascontiguousarray(np.asarray(pts, dtype=np.int64).reshape(-1, 3))
+    out = np.zeros((pts.shape[0], dims.norb, dims.norb), dtype=np.complex128)
+    dd = _dims_array(dims)
+    rc = (lib or _load()).oracle_sse_points_signed(_ptr(dd), _ptr(G), _ptr(Dp), _ptr(Dm), _ptr(dH), _ptr(nbr),
+                                                   float(np.real(alpha)), float(np.imag(alpha)), pts.shape[0],
+                                                   _ptr(pts), _ptr(out))
+    if rc:
+        raise RuntimeError(f"oracle_sse_points_signed failed with status {rc}")
     return out
 
 
@@ -191,6 +223,12 @@ class Bound:
 
     def sse_points(self, *a, **k):
         return sse_points(*a, lib=self.lib, **k)
+
+    def sse_forward_signed(self, *a, **k):
+        return sse_forward_signed(*a, lib=self.lib, **k)
+
+    def sse_points_signed(self, *a, **k):
+        return sse_points_signed(*a, lib=self.lib, **k)
 
     def sse_backward(self, *a, **k):
         return sse_backward(*a, lib=self.lib, **k)

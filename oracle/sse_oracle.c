@@ -13,6 +13,11 @@
  *                  D[q, m-1, a, n, i, j] * A[a,n,i] . G[(k-q) mod Nkz, e-s*m, nbr[a,n], 0]
  *                                        . A[a,n,j]^H
  *
+ * The *_signed functions take one table per sign of the frequency: the s = +1
+ * terms (G at e - m) read Dp[q, m-1, ...] (coefficient at +w_m), the s = -1
+ * terms (G at e + m) read Dm[q, m-1, ...] (coefficient at -w_m), which is the
+ * integral of Eq. 3 over signed frequencies on a grid of Nw positive ones.
+ *
  * A[a,n,i] is grad_i H for the pair (a, b = nbr[a,n]); grad_j H_ba = A[a,n,j]^H
  * because H is Hermitian.  Every product is an Norb x Norb complex matrix
  * product; D[...,i,j] is a complex scalar; only the diagonal block of Sigma is
@@ -107,8 +112,12 @@ static void acc_mul_adj(int64_t N, cplx d, const cplx* T, const double* Y, cplx*
         }
 }
 
-/* One output block Sigma[k,e,a] (Eq. 3), written to out as N*N complex. */
-static void sigma_block(const odims* d, const double* G, const double* D, const double* A,
+/* One output block Sigma[k,e,a] (Eq. 3), written to out as N*N complex.
+ * Eq. 3 integrates over signed frequencies; with the Nw stored frequencies
+ * w_m > 0 the s = +1 terms (G at e - m) carry the coefficient at +w_m (Dp) and
+ * the s = -1 terms (G at e + m) the coefficient at -w_m (Dm).  The north-star
+ * form reads the same table for both (Dm == Dp). */
+static void sigma_block(const odims* d, const double* G, const double* Dp, const double* Dm, const double* A,
                         const int32_t* nbr, cplx alpha, int64_t k, int64_t e, int64_t a,
                         cplx* acc, cplx* T, double* out) {
     const int64_t N = d->norb;
@@ -119,6 +128,7 @@ static void sigma_block(const odims* d, const double* G, const double* D, const 
             for (int s = +1; s >= -1; s -= 2) {
                 const int64_t ep = e - s * m;
                 if (ep < 0 || ep >= d->ne) continue;
+                const double* D = s > 0 ? Dp : Dm;
                 for (int64_t n = 0; n < d->nb; ++n) {
                     const int64_t b = nbr[a * d->nb + n];
                     const double* Gb = G + 2 * off_G(d, kp, ep, b);
@@ -148,14 +158,15 @@ int oracle_num_threads(void) {
 #endif
 }
 
-/* Sigma at a list of output points pts[p] = (k, e, a); out is [npts][norb][norb]. */
-int oracle_sse_points(const int64_t* dims, const double* G, const double* D, const double* A,
-                      const int32_t* nbr, double alpha_re, double alpha_im, int64_t npts,
-                      const int64_t* pts, double* out) {
+/* Sigma at a list of output points pts[p] = (k, e, a); out is [npts][norb][norb].
+ * Dp: coefficients at +w (terms with G at e - m), Dm: at -w (G at e + m). */
+int oracle_sse_points_signed(const int64_t* dims, const double* G, const double* Dp, const double* Dm,
+                             const double* A, const int32_t* nbr, double alpha_re, double alpha_im,
+                             int64_t npts, const int64_t* pts, double* out) {
     odims d;
     int rc = read_dims(dims, &d);
     if (rc) return rc;
-    if (!G || !D || !A || !nbr || (npts > 0 && (!pts || !out))) return 1;
+    if (!G || !Dp || !Dm || !A || !nbr || (npts > 0 && (!pts || !out))) return 1;
     if ((rc = check_nbr(&d, nbr))) return rc;
     for (int64_t p = 0; p < npts; ++p)
         if (pts[3 * p] < 0 || pts[3 * p] >= d.nkz || pts[3 * p + 1] < 0 || pts[3 * p + 1] >= d.ne ||
@@ -174,7 +185,7 @@ int oracle_sse_points(const int64_t* dims, const double* G, const double* D, con
         } else {
 #pragma omp for schedule(dynamic, 1)
             for (int64_t p = 0; p < npts; ++p)
-                sigma_block(&d, G, D, A, nbr, alpha, pts[3 * p], pts[3 * p + 1], pts[3 * p + 2], acc, T,
+                sigma_block(&d, G, Dp, Dm, A, nbr, alpha, pts[3 * p], pts[3 * p + 1], pts[3 * p + 2], acc, T,
                             out + 2 * NN * p);
         }
         free(acc);
@@ -183,13 +194,21 @@ int oracle_sse_points(const int64_t* dims, const double* G, const double* D, con
     return fail ? 7 : 0;
 }
 
-/* Full Sigma [nkz][ne][na][norb][norb]. */
-int oracle_sse_forward(const int64_t* dims, const double* G, const double* D, const double* A,
-                       const int32_t* nbr, double alpha_re, double alpha_im, double* Sigma) {
+/* The spec form: one coefficient table for both signs of the frequency. */
+int oracle_sse_points(const int64_t* dims, const double* G, const double* D, const double* A,
+                      const int32_t* nbr, double alpha_re, double alpha_im, int64_t npts,
+                      const int64_t* pts, double* out) {
+    return oracle_sse_points_signed(dims, G, D, D, A, nbr, alpha_re, alpha_im, npts, pts, out);
+}
+
+/* Full Sigma [nkz][ne][na][norb][norb]; Dp and Dm as for oracle_sse_points_signed. */
+int oracle_sse_forward_signed(const int64_t* dims, const double* G, const double* Dp, const double* Dm,
+                              const double* A, const int32_t* nbr, double alpha_re, double alpha_im,
+                              double* Sigma) {
     odims d;
     int rc = read_dims(dims, &d);
     if (rc) return rc;
-    if (!G || !D || !A || !nbr || !Sigma) return 1;
+    if (!G || !Dp || !Dm || !A || !nbr || !Sigma) return 1;
     if ((rc = check_nbr(&d, nbr))) return rc;
     const cplx alpha = { alpha_re, alpha_im };
     const int64_t NN = d.norb * d.norb;
@@ -206,13 +225,19 @@ int oracle_sse_forward(const int64_t* dims, const double* G, const double* D, co
 #pragma omp for schedule(dynamic, 4)
             for (int64_t x = 0; x < nblk; ++x) {
                 const int64_t a = x % d.na, e = (x / d.na) % d.ne, k = x / (d.na * d.ne);
-                sigma_block(&d, G, D, A, nbr, alpha, k, e, a, acc, T, Sigma + 2 * off_S(&d, k, e, a));
+                sigma_block(&d, G, Dp, Dm, A, nbr, alpha, k, e, a, acc, T, Sigma + 2 * off_S(&d, k, e, a));
             }
         }
         free(acc);
         free(T);
     }
     return fail ? 7 : 0;
+}
+
+/* Full Sigma, spec form (one table for both signs of the frequency). */
+int oracle_sse_forward(const int64_t* dims, const double* G, const double* D, const double* A,
+                       const int32_t* nbr, double alpha_re, double alpha_im, double* Sigma) {
+    return oracle_sse_forward_signed(dims, G, D, D, A, nbr, alpha_re, alpha_im, Sigma);
 }
 
 /*

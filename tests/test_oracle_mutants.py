@@ -12,6 +12,7 @@ import pytest
 
 from oracle import oracle
 import test_oracle_pins as pins
+import test_oracle_signed_pins as signed_pins
 
 MUTANTS = {
     "k_plus_q": ("((k - q) % d->nkz + d->nkz) % d->nkz", "((k + q) % d->nkz + d->nkz) % d->nkz"),
@@ -27,6 +28,8 @@ MUTANTS = {
     "first_neighbour_only": ("for (int64_t n = 0; n < d->nb; ++n) {", "for (int64_t n = 0; n < 1; ++n) {"),
     "right_product": ("mat_mul(N, A + 2 * off_A(d, a, n, i), Gb, T);", "mat_mul(N, Gb, A + 2 * off_A(d, a, n, i), T);"),
     "two_directions": ("for (int i = 0; i < 3; ++i) {\n                        mat_mul", "for (int i = 0; i < 2; ++i) {\n                        mat_mul"),
+    "signed_tables_swapped": ("const double* D = s > 0 ? Dp : Dm;", "const double* D = s > 0 ? Dm : Dp;"),
+    "signed_one_table": ("const double* D = s > 0 ? Dp : Dm;", "const double* D = Dp;"),
 }
 
 
@@ -42,6 +45,9 @@ def _pin_checks(lib):
         ("anti_hermitian", lambda: pins.test_anti_hermitian_output(lib, 1j, "anti")),
         ("homogeneity", lambda: pins.test_homogeneity_and_linearity(lib)),
         ("ne1_zero", lambda: pins.test_single_energy_point_is_zero(lib)),
+        ("signed_closed_form", lambda: signed_pins.test_single_block_closed_form_bit_exact(lib, 0, 4, 1, 2, 0, 0, 1)),
+        ("signed_reversal", lambda: signed_pins.test_energy_reversal_swaps_the_tables(lib)),
+        ("signed_brute_force", lambda: signed_pins.test_brute_force_python_loops(lib)),
     ]
     for name, fn in checks:
         try:

@@ -1,0 +1,114 @@
+"""Pins of the oracle's signed-frequency form of Eq. 3 (terms with G at E - w
+read the coefficient at +w, terms with G at E + w the one at -w) against facts
+that do not come from the oracle:
+  * closed form (bit exact) for a single G block and one coefficient per sign:
+    which branch reads which table, and the energy offsets of both;
+  * energy reversal: reversing the energy axis of G and swapping the two tables
+    reverses the energy axis of Sigma (a swapped branch breaks it);
+  * linearity in each table separately, and the reduction to the north-star
+    form when both tables are equal;
+  * term-by-term brute force in plain Python loops on a tiny case.
+"""
+import numpy as np
+import pytest
+
+from paper_1912_10024_amd.inputs import Dims, anti_hermitian_blocks, make_nbr
+
+SMALL = Dims(nkz=3, ne=9, nqz=3, nw=3, na=5, nb=2, norb=3, g_slots=1)
+
+
+def _rand(d: Dims, seed: int):
+    rng = np.random.default_rng(seed)
+
+    def cn(shape, s=1.0):
+        return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) * s
+
+    return (anti_hermitian_blocks(cn(d.g_shape)), cn(d.d_shape), cn(d.d_shape), cn(d.dh_shape, 0.3),
+            make_nbr(rng, d.na, d.nb))
+
+
+def _rel(x, y):
+    return np.linalg.norm((x - y).ravel()) / max(np.linalg.norm(y.ravel()), 1e-300)
+
+
+@pytest.mark.parametrize("k0,e0,q0,m0,n0,i0,j0", [(0, 4, 1, 2, 0, 0, 1), (2, 1, 2, 3, 1, 2, 2), (1, 7, 0, 1, 1, 1, 0)])
+def test_single_block_closed_form_bit_exact(oracle_lib, k0, e0, q0, m0, n0, i0, j0):
+    """G nonzero only at (k0, e0, b) with b the neighbour in slot n0 of atom a;
+    Dp = cp and Dm = cm at one (q0, m0, n0, i0, j0).  Then Sigma[k0+q0, e0+m0, a]
+    = alpha cp A_i G A_j^H (G at E - w, coefficient at +w) and
+    Sigma[k0+q0, e0-m0, a] = alpha cm A_i G A_j^H (G at E + w, at -w); zero
+    elsewhere.  Small integers keep every product exact."""
+    d = SMALL
+    rng = np.random.default_rng(k0 * 100 + e0)
+    nbr = np.array([[(a + 1) % d.na, (a + 2) % d.na] for a in range(d.na)], dtype=np.int32)
+    a = 3
+    b = int(nbr[a, n0])
+    G = np.zeros(d.g_shape, np.complex128)
+    Gb = rng.integers(-3, 4, (d.norb, d.norb)) + 1j * rng.integers(-3, 4, (d.norb, d.norb))
+    G[k0, e0, b, 0] = Gb
+    A = (rng.integers(-2, 3, d.dh_shape) + 1j * rng.integers(-2, 3, d.dh_shape)).astype(np.complex128)
+    Dp = np.zeros(d.d_shape, np.complex128)
+    Dm = np.zeros(d.d_shape, np.complex128)
+    cp, cm = 2 - 1j, -3 + 2j
+    Dp[q0, m0 - 1, a, n0, i0, j0] = cp
+    Dm[q0, m0 - 1, a, n0, i0, j0] = cm
+    alpha = 1j
+    S = oracle_lib.sse_forward_signed(d, G, Dp, Dm, A, nbr, alpha=alpha)
+    core = A[a, n0, i0] @ Gb @ A[a, n0, j0].conj().T
+    want = np.zeros_like(S)
+    k = (k0 + q0) % d.nkz
+    if e0 + m0 < d.ne:
+        want[k, e0 + m0, a] += alpha * cp * core
+    if e0 - m0 >= 0:
+        want[k, e0 - m0, a] += alpha * cm * core
+    assert np.array_equal(S, want)
+
+
+def test_energy_reversal_swaps_the_tables(oracle_lib):
+    d = SMALL
+    G, Dp, Dm, A, nbr = _rand(d, 3)
+    S = oracle_lib.sse_forward_signed(d, G, Dp, Dm, A, nbr)
+    Grev = np.ascontiguousarray(G[:, ::-1])
+    Srev = oracle_lib.sse_forward_signed(d, Grev, Dm, Dp, A, nbr)
+    assert _rel(Srev[:, ::-1], S) < 1e-14
+    # the same reversal without swapping the tables is a different result
+    Snot = oracle_lib.sse_forward_signed(d, Grev, Dp, Dm, A, nbr)
+    assert _rel(Snot[:, ::-1], S) > 1e-2
+
+
+def test_linearity_in_each_table_and_north_star_reduction(oracle_lib):
+    d = SMALL
+    G, Dp, Dm, A, nbr = _rand(d, 4)
+    Z = np.zeros_like(Dp)
+    S = oracle_lib.sse_forward_signed(d, G, Dp, Dm, A, nbr)
+    Sp = oracle_lib.sse_forward_signed(d, G, Dp, Z, A, nbr)
+    Sm = oracle_lib.sse_forward_signed(d, G, Z, Dm, A, nbr)
+    assert _rel(Sp + Sm, S) < 1e-14
+    assert np.array_equal(oracle_lib.sse_forward_signed(d, G, Dp, Dp, A, nbr), oracle_lib.sse_forward(d, G, Dp, A, nbr))
+    pts = [(0, 0, 0), (2, 8, 4), (1, 4, 2)]
+    P = oracle_lib.sse_points_signed(d, G, Dp, Dm, A, nbr, pts)
+    for p, (k, e, a) in enumerate(pts):
+        assert np.array_equal(P[p], S[k, e, a])
+
+
+def test_brute_force_python_loops(oracle_lib):
+    d = Dims(nkz=2, ne=5, nqz=2, nw=2, na=3, nb=2, norb=2, g_slots=1)
+    G, Dp, Dm, A, nbr = _rand(d, 5)
+    alpha = 0.7 - 0.2j
+    S = oracle_lib.sse_forward_signed(d, G, Dp, Dm, A, nbr, alpha=alpha)
+    want = np.zeros(d.sigma_shape, np.complex128)
+    for k in range(d.nkz):
+        for e in range(d.ne):
+            for a in range(d.na):
+                for q in range(d.nqz):
+                    for m in range(1, d.nw + 1):
+                        for ep, D in ((e - m, Dp), (e + m, Dm)):
+                            if not 0 <= ep < d.ne:
+                                continue
+                            for n in range(d.nb):
+                                Gb = G[(k - q) % d.nkz, ep, nbr[a, n], 0]
+                                for i in range(3):
+                                    for j in range(3):
+                                        want[k, e, a] += alpha * D[q, m - 1, a, n, i, j] * (
+                                            A[a, n, i] @ Gb @ A[a, n, j].conj().T)
+    assert _rel(S, want) < 1e-14
