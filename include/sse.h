@@ -66,7 +66,7 @@
 extern "C" {
 #endif
 
-#define SSE_ABI_VERSION 1
+#define SSE_ABI_VERSION 2
 
 typedef struct sse_dims {
     int64_t nkz;     /* electron momentum points kz (periodic grid)              */
@@ -134,6 +134,29 @@ int sse_effective_flops(const sse_dims* dims, double* f_eff);
 int sse_forward(const sse_dims* dims, const double* G, const double* D, const double* dH,
                 const int32_t* nbr, double alpha_re, double alpha_im, int precision,
                 double* Sigma, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Sigma of Eq. 3 with its frequency integral taken over both signs of w on a
+ * grid of Nw positive frequencies w_m = m (m = 1..Nw, energy steps):
+ *
+ *   Sigma[k,E,a] = alpha * sum_q sum_{m=1}^{Nw} sum_n sum_{i,j}
+ *                  ( [E-m >= 0] Dp[q,m-1,a,n,i,j] grad_iH . G[(k-q) mod Nkz, E-m, nbr[a,n], 0] . grad_jH^H
+ *                  + [E+m < NE] Dm[q,m-1,a,n,i,j] grad_iH . G[(k-q) mod Nkz, E+m, nbr[a,n], 0] . grad_jH^H )
+ *
+ * Dp holds the coefficients at +w_m (the terms with G at E - w) and Dm those at
+ * -w_m (G at E + w), both in D's layout [nqz][nw][na][nb][3][3]; how Dm is
+ * obtained (for instance from a lesser/greater symmetry of D) is the caller's.
+ * With Dm == Dp (the same pointer) this is sse_forward, in one pass.
+ * Otherwise the matrix-core shapes run one pass per table (the E - w terms
+ * write Sigma, the E + w terms add to it: twice the work of sse_forward); the
+ * other shapes take both tables in one fp64 pass.  Other arguments, layouts,
+ * precisions, workspace and errors as for sse_forward; Sigma must not overlap
+ * an input.
+ */
+int sse_forward_signed(const sse_dims* dims, const double* G, const double* Dp, const double* Dm,
+                       const double* dH, const int32_t* nbr, double alpha_re, double alpha_im,
+                       int precision, double* Sigma, void* workspace, size_t workspace_bytes,
+                       void* stream);
 
 /*
  * Adjoint of sse_forward (fp64) for a real scalar L, given dSigma = dL/dSigma

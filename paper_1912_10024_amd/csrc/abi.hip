@@ -99,12 +99,18 @@ int sse_effective_flops(const sse_dims* dims, double* f_eff) {
     return ok();
 }
 
-int sse_forward(const sse_dims* dims, const double* G, const double* D, const double* dH, const int32_t* nbr,
-                double alpha_re, double alpha_im, int precision, double* Sigma, void* workspace,
-                size_t workspace_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Sigma with the terms whose G sits at E - w reading Dp and those at E + w
+// reading Dm (the same table for the spec form)
+int forward_impl(const sse_dims* dims, const double* G, const double* Dp, const double* Dm, const double* dH,
+                 const int32_t* nbr, double alpha_re, double alpha_im, int precision, double* Sigma, void* workspace,
+                 size_t workspace_bytes, void* stream) {
     int rc = check_dims(dims);
     if (rc) return rc;
-    if (!G || !D || !dH || !nbr || !Sigma) return fail(SSE_ERR_NULL, "a tensor pointer is NULL");
+    if (!G || !Dp || !Dm || !dH || !nbr || !Sigma) return fail(SSE_ERR_NULL, "a tensor pointer is NULL");
     if (precision != SSE_FP64 && precision != SSE_FP32 && precision != SSE_FP16X2)
         return fail(SSE_ERR_PRECISION, "unknown precision %d", precision);
     size_t need = 0;
@@ -116,15 +122,41 @@ int sse_forward(const sse_dims* dims, const double* G, const double* D, const do
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e;
     if (sse::fwd_mfma_specialised(d)) {
-        e = sse::launch_fwd_mfma(d, precision, G, D, dH, nbr, alpha, Sigma, s);
+        if (Dm == Dp) {
+            e = sse::launch_fwd_mfma(d, precision, G, Dp, dH, nbr, alpha, Sigma, s);
+        } else {
+            // one GEMM per table: the E - w terms write Sigma, the E + w terms add to it
+            e = sse::launch_fwd_mfma(d, precision, G, Dp, dH, nbr, alpha, Sigma, s, sse::kBranchMinus);
+            if (e == hipSuccess)
+                e = sse::launch_fwd_mfma(d, precision, G, Dm, dH, nbr, alpha, Sigma, s,
+                                         sse::kBranchPlus | sse::kAccumulate);
+        }
     } else {
         if (precision != SSE_FP64)
             return fail(SSE_ERR_PRECISION, "precision %d has no kernel for these dims", precision);
         if (!sse::generic_supported(d)) return fail(SSE_ERR_DIMS, "no kernel for these dims");
-        e = sse::launch_fwd_generic(d, G, D, dH, nbr, alpha, Sigma, s);
+        e = sse::launch_fwd_generic(d, G, Dp, Dm, dH, nbr, alpha, Sigma, s);
     }
     if (e != hipSuccess) return hip_fail(e, "forward launch");
     return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+int sse_forward(const sse_dims* dims, const double* G, const double* D, const double* dH, const int32_t* nbr,
+                double alpha_re, double alpha_im, int precision, double* Sigma, void* workspace,
+                size_t workspace_bytes, void* stream) {
+    return forward_impl(dims, G, D, D, dH, nbr, alpha_re, alpha_im, precision, Sigma, workspace, workspace_bytes,
+                        stream);
+}
+
+int sse_forward_signed(const sse_dims* dims, const double* G, const double* Dp, const double* Dm, const double* dH,
+                       const int32_t* nbr, double alpha_re, double alpha_im, int precision, double* Sigma,
+                       void* workspace, size_t workspace_bytes, void* stream) {
+    return forward_impl(dims, G, Dp, Dm, dH, nbr, alpha_re, alpha_im, precision, Sigma, workspace, workspace_bytes,
+                        stream);
 }
 
 int sse_backward(const sse_dims* dims, const double* G, const double* D, const double* dH, const int32_t* nbr,

@@ -11,7 +11,8 @@ constexpr int kGenMaxPerThread = 4;  // norb^2 <= 1024
 }  // namespace
 
 __global__ __launch_bounds__(kGenThreads) void fwd_generic_kernel(Dims d, const double* __restrict__ G,
-                                                                  const double* __restrict__ D,
+                                                                  const double* __restrict__ Dp,
+                                                                  const double* __restrict__ Dm,
                                                                   const double* __restrict__ A,
                                                                   const int32_t* __restrict__ nbr, cd alpha,
                                                                   double* __restrict__ S) {
@@ -46,7 +47,8 @@ __global__ __launch_bounds__(kGenThreads) void fwd_generic_kernel(Dims d, const 
                             sT[x] = t;
                         }
                         __syncthreads();
-                        const double* Dq = D + 2 * off_D(d, q, w - 1, a, n);
+                        // G at E - w: coefficient at +w; G at E + w: coefficient at -w
+                        const double* Dq = (s > 0 ? Dp : Dm) + 2 * off_D(d, q, w - 1, a, n);
 #pragma unroll
                         for (int xi = 0; xi < kGenMaxPerThread; ++xi) {
                             const int x = tid + xi * kGenThreads;
@@ -74,12 +76,12 @@ __global__ __launch_bounds__(kGenThreads) void fwd_generic_kernel(Dims d, const 
     }
 }
 
-hipError_t launch_fwd_generic(const Dims& d, const double* G, const double* D, const double* A, const int32_t* nbr,
-                              cd alpha, double* S, hipStream_t stream) {
+hipError_t launch_fwd_generic(const Dims& d, const double* G, const double* Dp, const double* Dm, const double* A,
+                              const int32_t* nbr, cd alpha, double* S, hipStream_t stream) {
     const int64_t nblk = d.nkz * d.ne * d.na;
     const unsigned grid = (unsigned)(nblk < (int64_t)(1 << 30) ? nblk : (1 << 30));
     const size_t lds = sizeof(cd) * 4 * (size_t)(d.norb * d.norb);
-    hipLaunchKernelGGL(fwd_generic_kernel, dim3(grid), dim3(kGenThreads), lds, stream, d, G, D, A, nbr, alpha, S);
+    hipLaunchKernelGGL(fwd_generic_kernel, dim3(grid), dim3(kGenThreads), lds, stream, d, G, Dp, Dm, A, nbr, alpha, S);
     return hipGetLastError();
 }
 

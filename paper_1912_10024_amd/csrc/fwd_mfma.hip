@@ -267,7 +267,7 @@ struct ScatterPlan {
     }
 };
 
-template <int NORB, int NKZ, int NW, int NB, int EB, int PREC>
+template <int NORB, int NKZ, int NW, int NB, int EB, int PREC, int FLAGS>
 __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __restrict__ G,
                                                        const double* __restrict__ Dg,
                                                        const double* __restrict__ Ag,
@@ -649,6 +649,11 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     };
 
     // ---- add one V tile of energy block blk into the output ring
+    // Source energy es feeds Sigma at es + w through the terms with G at E - w
+    // and Sigma at es - w through those with G at E + w; FLAGS keeps either set
+    // (a compile-time choice, so the usual both-branch kernel carries no test).
+    constexpr bool minus = (FLAGS & kBranchMinus) != 0, plus = (FLAGS & kBranchPlus) != 0;
+    constexpr bool accumulate = (FLAGS & kAccumulate) != 0;
     // Branch-free: a contribution that falls off the energy grid, or comes from a
     // padding row or column, adds 0.0 to an in-range ring entry of the tile's own
     // k set (exact, and no entry of another concurrently scattering wave).
@@ -671,8 +676,8 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
             int plo = pbase - w, phi = pbase + w;
             plo += plo < 0 ? C::RING : 0;
             phi -= phi >= C::RING ? C::RING : 0;
-            atomicAdd(&sR[plo * C::RP + off], (ok && es - w >= 0) ? v4[v] : 0.0);
-            atomicAdd(&sR[phi * C::RP + off], (ok && es + w < NE) ? v4[v] : 0.0);
+            atomicAdd(&sR[plo * C::RP + off], (ok && plus && es - w >= 0) ? v4[v] : 0.0);
+            atomicAdd(&sR[phi * C::RP + off], (ok && minus && es + w < NE) ? v4[v] : 0.0);
         }
     };
     constexpr ScatterPlan<C> plan{};
@@ -696,7 +701,13 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
             const cd v{slot[0], slot[1]};
             slot[0] = 0.0;
             slot[1] = 0.0;
-            cstore(S, (((int64_t)k * NE + e) * na + a) * C::NN + r * NORB + c, cmul(alpha, v));
+            const int64_t o = (((int64_t)k * NE + e) * na + a) * C::NN + r * NORB + c;
+            cd out = cmul(alpha, v);
+            if constexpr (accumulate) {
+                const cd old = cload(S, o);
+                out = cd{old.re + out.re, old.im + out.im};
+            }
+            cstore(S, o, out);
         }
     };
 
@@ -746,11 +757,11 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     write_planes(nblk * EB - NW, NE);
 }
 
-template <int NORB, int NKZ, int NW, int NB, int EB, int PREC>
-static hipError_t launch_fwd(const Dims& d, const double* G, const double* D, const double* A, const int32_t* nbr,
-                             cd alpha, double* S, hipStream_t stream) {
+template <int NORB, int NKZ, int NW, int NB, int EB, int PREC, int FLAGS>
+static hipError_t launch_fwd_flags(const Dims& d, const double* G, const double* D, const double* A,
+                                   const int32_t* nbr, cd alpha, double* S, hipStream_t stream) {
     using C = Fwd64<NORB, NKZ, NW, NB, EB, PREC>;
-    auto kern = fwd_mfma_kernel<NORB, NKZ, NW, NB, EB, PREC>;
+    auto kern = fwd_mfma_kernel<NORB, NKZ, NW, NB, EB, PREC, FLAGS>;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -763,6 +774,20 @@ static hipError_t launch_fwd(const Dims& d, const double* G, const double* D, co
     return hipGetLastError();
 }
 
+// the branch sets with a kernel instance: both (one pass), and the two passes
+// of the signed form (E - w terms written, E + w terms added)
+template <int NORB, int NKZ, int NW, int NB, int EB, int PREC>
+static hipError_t launch_fwd(const Dims& d, const double* G, const double* D, const double* A, const int32_t* nbr,
+                             cd alpha, double* S, hipStream_t stream, int flags) {
+    constexpr int kBoth = kBranchMinus | kBranchPlus, kPlusAdd = kBranchPlus | kAccumulate;
+    if (flags == kBoth) return launch_fwd_flags<NORB, NKZ, NW, NB, EB, PREC, kBoth>(d, G, D, A, nbr, alpha, S, stream);
+    if (flags == kBranchMinus)
+        return launch_fwd_flags<NORB, NKZ, NW, NB, EB, PREC, kBranchMinus>(d, G, D, A, nbr, alpha, S, stream);
+    if (flags == kPlusAdd)
+        return launch_fwd_flags<NORB, NKZ, NW, NB, EB, PREC, kPlusAdd>(d, G, D, A, nbr, alpha, S, stream);
+    return hipErrorInvalidValue;
+}
+
 bool fwd_mfma_specialised(const Dims& d) {
     if (d.ne >= (int64_t(1) << 28)) return false;  // 32-bit chunk indices
     return (d.norb == 10 && d.nkz == 7 && d.nw == 10 && d.nb == 4) || (d.norb == 4 && d.nkz == 3 && d.nw == 2 && d.nb == 4) ||
@@ -771,21 +796,21 @@ bool fwd_mfma_specialised(const Dims& d) {
 
 template <int PREC>
 static hipError_t dispatch_fwd(const Dims& d, const double* G, const double* D, const double* A, const int32_t* nbr,
-                               cd alpha, double* S, hipStream_t stream) {
+                               cd alpha, double* S, hipStream_t stream, int flags) {
     if (d.norb == 10 && d.nkz == 7 && d.nw == 10 && d.nb == 4)
-        return launch_fwd<10, 7, 10, 4, 8, PREC>(d, G, D, A, nbr, alpha, S, stream);
+        return launch_fwd<10, 7, 10, 4, 8, PREC>(d, G, D, A, nbr, alpha, S, stream, flags);
     if (d.norb == 10 && d.nkz == 7 && d.nw == 10 && d.nb == 3)
-        return launch_fwd<10, 7, 10, 3, 8, PREC>(d, G, D, A, nbr, alpha, S, stream);
+        return launch_fwd<10, 7, 10, 3, 8, PREC>(d, G, D, A, nbr, alpha, S, stream, flags);
     if (d.norb == 4 && d.nkz == 3 && d.nw == 2 && d.nb == 4)
-        return launch_fwd<4, 3, 2, 4, 8, PREC>(d, G, D, A, nbr, alpha, S, stream);
+        return launch_fwd<4, 3, 2, 4, 8, PREC>(d, G, D, A, nbr, alpha, S, stream, flags);
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_fwd_mfma(const Dims& d, int precision, const double* G, const double* D, const double* A,
-                           const int32_t* nbr, cd alpha, double* S, hipStream_t stream) {
-    if (precision == SSE_FP64) return dispatch_fwd<SSE_FP64>(d, G, D, A, nbr, alpha, S, stream);
-    if (precision == SSE_FP32) return dispatch_fwd<SSE_FP32>(d, G, D, A, nbr, alpha, S, stream);
-    if (precision == SSE_FP16X2) return dispatch_fwd<SSE_FP16X2>(d, G, D, A, nbr, alpha, S, stream);
+                           const int32_t* nbr, cd alpha, double* S, hipStream_t stream, int flags) {
+    if (precision == SSE_FP64) return dispatch_fwd<SSE_FP64>(d, G, D, A, nbr, alpha, S, stream, flags);
+    if (precision == SSE_FP32) return dispatch_fwd<SSE_FP32>(d, G, D, A, nbr, alpha, S, stream, flags);
+    if (precision == SSE_FP16X2) return dispatch_fwd<SSE_FP16X2>(d, G, D, A, nbr, alpha, S, stream, flags);
     return hipErrorInvalidValue;
 }
 

@@ -5,15 +5,26 @@
 
 namespace sse {
 
-// direct term-by-term fp64 forward (any shape with norb^2 <= 1024)
-bool generic_supported(const Dims& d);
-hipError_t launch_fwd_generic(const Dims& d, const double* G, const double* D, const double* A, const int32_t* nbr,
-                              cd alpha, double* S, hipStream_t stream);
+// Energy branches of Eq. 3 on a grid of positive frequencies w: the terms with
+// G at E - w (coefficient at +w) and those with G at E + w (coefficient at -w)
+constexpr int kBranchMinus = 1;  // terms with G at E - w
+constexpr int kBranchPlus = 2;   // terms with G at E + w
+constexpr int kAccumulate = 4;   // Sigma += result instead of Sigma = result
 
-// matrix-core forward (fp64 or fp32 operands) for the shapes it is instantiated for
+// direct term-by-term fp64 forward (any shape with norb^2 <= 1024); the terms
+// with G at E - w read Dp, those with G at E + w read Dm (Dm == Dp: the
+// spec form)
+bool generic_supported(const Dims& d);
+hipError_t launch_fwd_generic(const Dims& d, const double* G, const double* Dp, const double* Dm, const double* A,
+                              const int32_t* nbr, cd alpha, double* S, hipStream_t stream);
+
+// matrix-core forward (fp64, fp32 or fp16 hi/lo operands) for the shapes it is
+// instantiated for; flags selects the energy branches (kBranchMinus,
+// kBranchPlus) and whether the result is added to Sigma (kAccumulate)
 bool fwd_mfma_specialised(const Dims& d);
 hipError_t launch_fwd_mfma(const Dims& d, int precision, const double* G, const double* D, const double* A,
-                           const int32_t* nbr, cd alpha, double* S, hipStream_t stream);
+                           const int32_t* nbr, cd alpha, double* S, hipStream_t stream,
+                           int flags = kBranchMinus | kBranchPlus);
 
 // adjoint (fp64): reverse adjacency in the workspace, then dG/d gradH per neighbour atom and dD per edge
 size_t bwd_workspace_bytes(const Dims& d);

@@ -103,6 +103,21 @@ def combine_d(Dfull: torch.Tensor, nbr: torch.Tensor) -> torch.Tensor:
 
 def forward(G, D, dH, nbr, alpha=1j, precision: str = "fp64", out=None, ws=None) -> torch.Tensor:
     """Sigma[nkz, ne, na, norb, norb] = Eq. 3 (one of lesser/greater)."""
+    return _forward(G, D, D, dH, nbr, alpha, precision, out, ws)
+
+
+def forward_signed(G, Dp, Dm, dH, nbr, alpha=1j, precision: str = "fp64", out=None, ws=None) -> torch.Tensor:
+    """Sigma of Eq. 3 over both signs of the frequency: the terms with G at
+    E - w read Dp (coefficients at +w), those with G at E + w read Dm (at -w);
+    both in D's layout.  Dm is Dp gives forward()."""
+    if Dm is not Dp:
+        _check_tensor(Dm, "Dm")
+        if Dm.shape != Dp.shape:
+            raise ValueError(f"Dm must have Dp's shape {tuple(Dp.shape)}")
+    return _forward(G, Dp, Dm, dH, nbr, alpha, precision, out, ws)
+
+
+def _forward(G, D, Dm, dH, nbr, alpha, precision, out, ws) -> torch.Tensor:
     d = dims_of(G, D, dH, nbr)
     for t, n in ((G, "G"), (D, "D"), (dH, "dH")):
         _check_tensor(t, n)
@@ -120,9 +135,14 @@ def forward(G, D, dH, nbr, alpha=1j, precision: str = "fp64", out=None, ws=None)
     lib = _lib.load()
     cd = _lib.SSEDims.of(d)
     a = complex(alpha)
-    rc = lib.sse_forward(ctypes.byref(cd), _ptr(G), _ptr(D), _ptr(dH), _ptr(nbr), a.real, a.imag,
-                         PRECISIONS[precision], _ptr(out), _ptr(ws), ws.numel(), _stream(G.device))
-    _raise(rc, "sse_forward")
+    if Dm is D:
+        rc = lib.sse_forward(ctypes.byref(cd), _ptr(G), _ptr(D), _ptr(dH), _ptr(nbr), a.real, a.imag,
+                             PRECISIONS[precision], _ptr(out), _ptr(ws), ws.numel(), _stream(G.device))
+        _raise(rc, "sse_forward")
+    else:
+        rc = lib.sse_forward_signed(ctypes.byref(cd), _ptr(G), _ptr(D), _ptr(Dm), _ptr(dH), _ptr(nbr), a.real, a.imag,
+                                    PRECISIONS[precision], _ptr(out), _ptr(ws), ws.numel(), _stream(G.device))
+        _raise(rc, "sse_forward_signed")
     return out
 
 

@@ -29,8 +29,8 @@ def lib():
 
 def test_exports_every_declared_symbol(lib):
     declared = _declared()
-    assert {"sse_forward", "sse_backward", "sse_workspace_bytes", "sse_check_nbr", "sse_effective_flops",
-            "sse_last_error", "sse_abi_version"} <= declared
+    assert {"sse_forward", "sse_forward_signed", "sse_backward", "sse_workspace_bytes", "sse_check_nbr",
+            "sse_effective_flops", "sse_last_error", "sse_abi_version"} <= declared
     for name in declared:
         assert hasattr(lib, name), name
     assert set(_lib.EXPORTS) <= declared
@@ -111,3 +111,17 @@ def test_phonon_forward_rejects_bad_input(lib):
         ptrs = [P(1)] * 5
         ptrs[i] = None
         assert lib.sse_phonon_forward(ctypes.byref(good), *ptrs[:4], 0.0, -1.0, ptrs[4], None) == _lib.SSE_ERR_NULL
+
+
+def test_signed_forward_rejects_bad_input(lib):
+    P = ctypes.c_void_p
+    good = _lib.SSEDims.of(CONFIGS["tiny"])
+    bad = _lib.SSEDims(3, 4, 2, 2, 3, 2, 2, 1)  # nqz != nkz
+    args = lambda: [P(1)] * 6
+    assert lib.sse_forward_signed(ctypes.byref(bad), *args()[:5], 0.0, 1.0, 0, P(1), None, 0, None) == _lib.SSE_ERR_DIMS
+    for i in range(5):
+        ptrs = args()[:5]
+        ptrs[i] = None  # G, Dp, Dm, dH, nbr
+        assert lib.sse_forward_signed(ctypes.byref(good), *ptrs, 0.0, 1.0, 0, P(1), None, 0, None) == _lib.SSE_ERR_NULL
+    assert lib.sse_forward_signed(ctypes.byref(good), *args()[:5], 0.0, 1.0, 0, None, None, 0, None) == _lib.SSE_ERR_NULL
+    assert lib.sse_forward_signed(ctypes.byref(good), *args()[:5], 0.0, 1.0, 9, P(1), None, 0, None) == _lib.SSE_ERR_PRECISION

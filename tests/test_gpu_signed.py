@@ -1,0 +1,98 @@
+"""GPU parity of the signed-frequency form of Eq. 3 (sse_forward_signed: the
+terms with G at E - w read Dp, those with G at E + w read Dm) against the CPU
+oracle's signed form: full outputs on every kernel family and precision,
+sampled blocks at the mid workload, and the reduction to sse_forward."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle
+from paper_1912_10024_amd import sse
+from paper_1912_10024_amd.inputs import CONFIGS, CONFIG_INDEX, Dims, anti_hermitian_blocks, generate, make_nbr
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-6, "fp16x2": 1e-6}
+
+
+def _rand(d: Dims, seed: int):
+    rng = np.random.default_rng(seed)
+
+    def cn(shape, s=1.0):
+        return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) * s
+
+    return dict(G=anti_hermitian_blocks(cn(d.g_shape)), Dp=cn(d.d_shape), Dm=cn(d.d_shape), dH=cn(d.dh_shape, 0.1),
+                nbr=make_nbr(rng, d.na, d.nb))
+
+
+def _rel(x, y):
+    return float(np.linalg.norm((x - y).ravel()) / max(np.linalg.norm(y.ravel()), 1e-300))
+
+
+SHAPES = [
+    (Dims(nkz=7, ne=21, nqz=7, nw=10, na=5, nb=4, norb=10, g_slots=1), 1, ("fp64", "fp32", "fp16x2")),  # matrix cores
+    (Dims(nkz=7, ne=13, nqz=7, nw=10, na=4, nb=3, norb=10, g_slots=2), 2, ("fp64", "fp16x2")),          # nb 3
+    (Dims(nkz=3, ne=19, nqz=3, nw=2, na=9, nb=4, norb=4, g_slots=1), 3, ("fp64", "fp32")),              # small instance
+    (Dims(nkz=3, ne=11, nqz=3, nw=4, na=6, nb=3, norb=5, g_slots=2), 4, ("fp64",)),                      # vector-ALU kernel
+]
+CASES = [(d, s, p) for d, s, ps in SHAPES for p in ps]
+
+
+@pytest.mark.parametrize("dims,seed,precision", CASES, ids=[f"s{s}-{p}" for _, s, p in CASES])
+def test_signed_matches_oracle_full(dims, seed, precision):
+    print(f"[gpu] signed forward dims={dims.as_tuple()} seed={seed} precision={precision}", flush=True)
+    inp = _rand(dims, seed)
+    alpha = 0.3 + 0.8j
+    t = {k: torch.from_numpy(v).cuda() for k, v in inp.items()}
+    out = torch.full(dims.sigma_shape, complex(float("nan"), float("nan")), dtype=torch.complex128, device="cuda")
+    S = sse.forward_signed(t["G"], t["Dp"], t["Dm"], t["dH"], t["nbr"], alpha=alpha, precision=precision, out=out)
+    torch.cuda.synchronize()
+    got = S.cpu().numpy()
+    ref = oracle.sse_forward_signed(dims, inp["G"], inp["Dp"], inp["Dm"], inp["dH"], inp["nbr"], alpha=alpha)
+    err = _rel(got, ref)
+    print(f"  rel err {err:.3e}", flush=True)
+    assert np.isfinite(got).all()  # the first pass overwrites every output element
+    assert err <= TOL[precision]
+
+
+@pytest.mark.parametrize("dims", [SHAPES[0][0], SHAPES[3][0]], ids=["mfma", "generic"])
+def test_same_table_is_forward(dims):
+    inp = _rand(dims, 5)
+    t = {k: torch.from_numpy(v).cuda() for k, v in inp.items()}
+    S1 = sse.forward(t["G"], t["Dp"], t["dH"], t["nbr"])
+    S2 = sse.forward_signed(t["G"], t["Dp"], t["Dp"], t["dH"], t["nbr"])
+    # a copy of the table takes the two-pass (or two-table) route: same sum, other order
+    S3 = sse.forward_signed(t["G"], t["Dp"], t["Dp"].clone(), t["dH"], t["nbr"])
+    torch.cuda.synchronize()
+    assert torch.equal(S1, S2)
+    assert _rel(S3.cpu().numpy(), S1.cpu().numpy()) <= 1e-14
+
+
+def test_zero_plus_table_keeps_only_minus_branch():
+    """Dm = 0: only the terms with G at E - w remain, so the lowest energy of
+    Sigma (no E - w >= 0 for w >= 1) is exactly zero."""
+    d = SHAPES[0][0]
+    inp = _rand(d, 6)
+    t = {k: torch.from_numpy(v).cuda() for k, v in inp.items()}
+    S = sse.forward_signed(t["G"], t["Dp"], torch.zeros_like(t["Dp"]), t["dH"], t["nbr"]).cpu().numpy()
+    assert np.array_equal(S[:, 0], np.zeros_like(S[:, 0]))
+    ref = oracle.sse_forward_signed(d, inp["G"], inp["Dp"], np.zeros_like(inp["Dp"]), inp["dH"], inp["nbr"])
+    assert _rel(S, ref) <= TOL["fp64"]
+
+
+def test_mid_config_sampled_blocks():
+    d = CONFIGS["mid"]
+    print(f"[gpu] signed forward mid sampled parity dims={d.as_tuple()}", flush=True)
+    inp = generate(d, CONFIG_INDEX["mid"], which=("nbr", "G<", "D<", "D>", "dH"))
+    t = {k: torch.from_numpy(v).cuda() for k, v in inp.items()}
+    S = sse.forward_signed(t["G<"], t["D<"], t["D>"], t["dH"], t["nbr"])
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(99)
+    pts = [(0, 0, 0), (d.nkz - 1, d.ne - 1, d.na - 1), (3, 5, 17), (6, d.ne - 3, 1000)]
+    pts += [tuple(int(x) for x in (rng.integers(d.nkz), rng.integers(d.ne), rng.integers(d.na))) for _ in range(20)]
+    ref = oracle.sse_points_signed(d, inp["G<"], inp["D<"], inp["D>"], inp["dH"], inp["nbr"], pts)
+    idx = torch.tensor(pts, device=S.device)
+    got = S[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy()
+    err = _rel(got, ref)
+    print(f"  sampled rel err {err:.3e}", flush=True)
+    assert err <= TOL["fp64"]
