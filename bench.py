@@ -278,8 +278,8 @@ def adjoint_record(args, sse, dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
-                          "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the self-energy kernels run on one GPU per process; there is no multi-GPU path "
+                                   "(the sharding design is in the design notes)", "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
 
