@@ -46,6 +46,8 @@ def parse():
     p.add_argument("--no-phonon", action="store_true", help="skip the phonon self-energy timing")
     p.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing (mid workload)")
     p.add_argument("--only-phonon", action="store_true", help="time only the phonon self-energy (profiling runs)")
+    p.add_argument("--only-adjoint", action="store_true",
+                   help="time only the adjoint on the mid workload and its forward (profiling runs)")
     p.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                    help="only run a plain device copy of this many GiB (scales HBM byte counters)")
     return p.parse_args()
@@ -297,6 +299,14 @@ def main():
 
     d = CONFIGS[args.config]
     dev = torch.device("cuda:0")
+    if args.only_adjoint:
+        rec = adjoint_record(args, sse, dev)
+        print(json.dumps({"metric": "adjoint time, all three gradients (mid workload)",
+                          "value": rec["ms_all_gradients"], "unit": "ms", "n_gpus": 1, "steps": args.steps,
+                          "warmup": args.warmup, "ms_per_step": rec["ms_all_gradients"], "higher_is_better": False,
+                          "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+                          "config": {"workload": rec["workload"]}, "adjoint": rec}), flush=True)
+        return
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     t_gen = time.perf_counter()
     inp = generate_device(d, CONFIG_INDEX[args.config], device=dev)

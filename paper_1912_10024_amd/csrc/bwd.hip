@@ -89,7 +89,15 @@ __global__ void zero_i32_kernel(int64_t n, int32_t* p) {
     for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) p[x] = 0;
 }
 
-size_t bwd_workspace_bytes(const Dims& d) { return sizeof(int32_t) * (size_t)(3 * d.na + 1 + d.na * d.nb) + 256; }
+// ws layout after the reverse adjacency (256-byte aligned): the d gradH sums of
+// every edge, one set per momentum k' (complex [nkz][na*nb][3][norb][norb]),
+// added in k' order by bwd_dh_reduce_kernel
+static size_t bwd_csr_bytes(const Dims& d) {
+    return (sizeof(int32_t) * (size_t)(3 * d.na + 1 + d.na * d.nb) + 255) / 256 * 256;
+}
+size_t bwd_workspace_bytes(const Dims& d) {
+    return bwd_csr_bytes(d) + sizeof(cd) * (size_t)(d.nkz * d.na * d.nb * 3 * d.norb * d.norb);
+}
 
 // --------------------------------------------------------------- W and Y of one source point
 // A zero row read in place of g blocks outside the energy grid, so the loads of
@@ -148,7 +156,7 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_dg_dh_kernel(Dims d, const do
                                                                 const double* __restrict__ gS, cd calpha,
                                                                 const int32_t* __restrict__ offset,
                                                                 const int32_t* __restrict__ edges,
-                                                                double* __restrict__ dG, double* __restrict__ dA) {
+                                                                double* __restrict__ dG, double* __restrict__ dApart) {
     extern __shared__ double smem[];
     const int N = (int)d.norb, NN = N * N;
     const int nqw = (int)(d.nqz * d.nw);
@@ -163,18 +171,23 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_dg_dh_kernel(Dims d, const do
     cd* sY1 = sT;                           // [9][N][N]   second half of the frequency sum of Y; shares
                                             // sT, sC, sE (9 N^2), which are written only after the merge
     const int tid = threadIdx.x;
-    const int64_t b = blockIdx.x;
-    if (b >= d.na) return;
+    // One workgroup per (neighbour atom b, momentum k'): Nkz times as many
+    // equal workgroups as atoms, so the launch has no partly filled last round.
+    // The Nkz workgroups of one atom get ids on the same XCD (they read the
+    // same D, grad H and g blocks).
+    const int64_t bid = blockIdx.x, span = 8 * d.nkz;
+    const int64_t b = (bid / span) * 8 + bid % 8;
+    const int64_t kp = (bid % span) / 8;
+    if (b >= d.na) return;  // uniform for the workgroup, before any barrier
     const int32_t e_lo = offset[b], e_hi = offset[b + 1];
 
     // slots >= 1 of dG are not read by the forward map: zero
     if (dG && (d.gs > 1 || e_lo == e_hi)) {
-        for (int64_t kp = 0; kp < d.nkz; ++kp)
-            for (int64_t ep = 0; ep < d.ne; ++ep) {
-                const int64_t base = off_G(d, kp, ep, b);
-                const int64_t from = (e_lo == e_hi) ? 0 : NN;
-                for (int64_t x = from + tid; x < d.gs * NN; x += kBwdThreads) cstore(dG, base + x, cd{0.0, 0.0});
-            }
+        for (int64_t ep = 0; ep < d.ne; ++ep) {
+            const int64_t base = off_G(d, kp, ep, b);
+            const int64_t from = (e_lo == e_hi) ? 0 : NN;
+            for (int64_t x = from + tid; x < d.gs * NN; x += kBwdThreads) cstore(dG, base + x, cd{0.0, 0.0});
+        }
     }
     for (int32_t ei = e_lo; ei < e_hi; ++ei) {
         const int32_t edge = edges[ei];
@@ -189,73 +202,92 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_dg_dh_kernel(Dims d, const do
             sdA[x] = cd{0.0, 0.0};
         }
         __syncthreads();
-        for (int64_t kp = 0; kp < d.nkz; ++kp)
-            for (int64_t ep = 0; ep < d.ne; ++ep) {
-                // Y: threads [0, NN) sum the frequencies up to Nw/2, threads
-                // [kYHalf, kYHalf + NN) the rest; the halves are then added
-                const int yh = tid >= kYHalf ? 1 : 0;
-                for (int yx = tid - yh * kYHalf; yx < NN; yx += kYHalf) {
-                    cd y[9];
-                    const int64_t w_mid = d.nw / 2;
-                    compute_y(d, gS, a, kp, ep, sDn, yh ? w_mid + 1 : 1, yh ? d.nw : w_mid, yx, y);
-                    cd* dst = yh ? sY1 : sY;
+        for (int64_t ep = 0; ep < d.ne; ++ep) {
+            // Y: threads [0, NN) sum the frequencies up to Nw/2, threads
+            // [kYHalf, kYHalf + NN) the rest; the halves are then added
+            const int yh = tid >= kYHalf ? 1 : 0;
+            for (int yx = tid - yh * kYHalf; yx < NN; yx += kYHalf) {
+                cd y[9];
+                const int64_t w_mid = d.nw / 2;
+                compute_y(d, gS, a, kp, ep, sDn, yh ? w_mid + 1 : 1, yh ? d.nw : w_mid, yx, y);
+                cd* dst = yh ? sY1 : sY;
 #pragma unroll
-                    for (int ij = 0; ij < 9; ++ij) dst[ij * NN + yx] = y[ij];
-                    if (!yh) sB[yx] = cload(G, off_G(d, kp, ep, b) + yx);
-                }
-                __syncthreads();
-                for (int x = tid; x < 9 * NN; x += kBwdThreads) {
-                    const cd u = sY[x], v = sY1[x];
-                    sY[x] = cmul(calpha, cd{u.re + v.re, u.im + v.im});
-                }
-                __syncthreads();
-                // T_j = sum_i A_i^H Y_ij ; C_j = A_j B^H ; E_i = A_i B
-                for (int x = tid; x < 9 * NN; x += kBwdThreads) {
-                    const int m = x / NN, rc = x % NN, r = rc / N, c = rc % N;
-                    cd s{0.0, 0.0};
-                    if (m < 3) {
-                        const int j = m;
-                        for (int i = 0; i < 3; ++i)
-                            for (int t = 0; t < N; ++t) cfma_conja(s, sA[i * NN + t * N + r], sY[(i * 3 + j) * NN + t * N + c]);
-                        sT[j * NN + rc] = s;
-                    } else if (m < 6) {
-                        const int j = m - 3;
-                        for (int t = 0; t < N; ++t) cfma_conj(s, sA[j * NN + r * N + t], sB[c * N + t]);
-                        sC[j * NN + rc] = s;
-                    } else {
-                        const int i = m - 6;
-                        for (int t = 0; t < N; ++t) cfma(s, sA[i * NN + r * N + t], sB[t * N + c]);
-                        sE[i * NN + rc] = s;
-                    }
-                }
-                __syncthreads();
-                // dG[k',E',b] (+)= sum_j T_j A_j
-                for (int x = tid; dG && x < NN; x += kBwdThreads) {
-                    const int t = x / N, u = x % N;
-                    cd s{0.0, 0.0};
-                    for (int j = 0; j < 3; ++j)
-                        for (int c = 0; c < N; ++c) cfma(s, sT[j * NN + t * N + c], sA[j * NN + c * N + u]);
-                    const int64_t o = off_G(d, kp, ep, b) + x;
-                    if (ei != e_lo) {
-                        const cd prev = cload(dG, o);
-                        s.re += prev.re;
-                        s.im += prev.im;
-                    }
-                    cstore(dG, o, s);
-                }
-                // d gradH_m += sum_j Y_mj C_j + sum_i Y_im^H E_i
-                for (int x = tid; dA && x < 3 * NN; x += kBwdThreads) {
-                    const int m = x / NN, rc = x % NN, r = rc / N, c = rc % N;
-                    cd s = sdA[x];
-                    for (int j = 0; j < 3; ++j)
-                        for (int t = 0; t < N; ++t) cfma(s, sY[(m * 3 + j) * NN + r * N + t], sC[j * NN + t * N + c]);
-                    for (int i = 0; i < 3; ++i)
-                        for (int t = 0; t < N; ++t) cfma_conja(s, sY[(i * 3 + m) * NN + t * N + r], sE[i * NN + t * N + c]);
-                    sdA[x] = s;
-                }
-                __syncthreads();
+                for (int ij = 0; ij < 9; ++ij) dst[ij * NN + yx] = y[ij];
+                if (!yh) sB[yx] = cload(G, off_G(d, kp, ep, b) + yx);
             }
-        for (int x = tid; dA && x < 3 * NN; x += kBwdThreads) cstore(dA, off_A(d, a, n, 0) + x, sdA[x]);
+            __syncthreads();
+            for (int x = tid; x < 9 * NN; x += kBwdThreads) {
+                const cd u = sY[x], v = sY1[x];
+                sY[x] = cmul(calpha, cd{u.re + v.re, u.im + v.im});
+            }
+            __syncthreads();
+            // T_j = sum_i A_i^H Y_ij ; C_j = A_j B^H ; E_i = A_i B
+            for (int x = tid; x < 9 * NN; x += kBwdThreads) {
+                const int m = x / NN, rc = x % NN, r = rc / N, c = rc % N;
+                cd s{0.0, 0.0};
+                if (m < 3) {
+                    const int j = m;
+                    for (int i = 0; i < 3; ++i)
+                        for (int t = 0; t < N; ++t) cfma_conja(s, sA[i * NN + t * N + r], sY[(i * 3 + j) * NN + t * N + c]);
+                    sT[j * NN + rc] = s;
+                } else if (m < 6) {
+                    const int j = m - 3;
+                    for (int t = 0; t < N; ++t) cfma_conj(s, sA[j * NN + r * N + t], sB[c * N + t]);
+                    sC[j * NN + rc] = s;
+                } else {
+                    const int i = m - 6;
+                    for (int t = 0; t < N; ++t) cfma(s, sA[i * NN + r * N + t], sB[t * N + c]);
+                    sE[i * NN + rc] = s;
+                }
+            }
+            __syncthreads();
+            // dG[k',E',b] (+)= sum_j T_j A_j
+            for (int x = tid; dG && x < NN; x += kBwdThreads) {
+                const int t = x / N, u = x % N;
+                cd s{0.0, 0.0};
+                for (int j = 0; j < 3; ++j)
+                    for (int c = 0; c < N; ++c) cfma(s, sT[j * NN + t * N + c], sA[j * NN + c * N + u]);
+                const int64_t o = off_G(d, kp, ep, b) + x;
+                if (ei != e_lo) {
+                    const cd prev = cload(dG, o);
+                    s.re += prev.re;
+                    s.im += prev.im;
+                }
+                cstore(dG, o, s);
+            }
+            // d gradH_m += sum_j Y_mj C_j + sum_i Y_im^H E_i
+            for (int x = tid; dApart && x < 3 * NN; x += kBwdThreads) {
+                const int m = x / NN, rc = x % NN, r = rc / N, c = rc % N;
+                cd s = sdA[x];
+                for (int j = 0; j < 3; ++j)
+                    for (int t = 0; t < N; ++t) cfma(s, sY[(m * 3 + j) * NN + r * N + t], sC[j * NN + t * N + c]);
+                for (int i = 0; i < 3; ++i)
+                    for (int t = 0; t < N; ++t) cfma_conja(s, sY[(i * 3 + m) * NN + t * N + r], sE[i * NN + t * N + c]);
+                sdA[x] = s;
+            }
+            __syncthreads();
+        }
+        // this momentum's share of the edge's d gradH (edge index a * nb + n)
+        for (int x = tid; dApart && x < 3 * NN; x += kBwdThreads)
+            cstore(dApart, (kp * d.na * d.nb + edge) * 3 * NN + x, sdA[x]);
+    }
+}
+
+// d gradH of every edge (a, n): its Nkz per-k' sums added in k' order; an edge
+// whose neighbour entry lies outside [0, na) has no terms and gets zero
+__global__ void bwd_dh_reduce_kernel(Dims d, const int32_t* __restrict__ nbr, const double* __restrict__ dApart,
+                                     double* __restrict__ dA) {
+    const int64_t NN3 = 3 * d.norb * d.norb, per_k = d.na * d.nb * NN3;
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < per_k; x += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t b = nbr[x / NN3];
+        cd s{0.0, 0.0};
+        if (b >= 0 && b < d.na)
+            for (int64_t kp = 0; kp < d.nkz; ++kp) {
+                const cd v = cload(dApart, kp * per_k + x);
+                s.re += v.re;
+                s.im += v.im;
+            }
+        cstore(dA, x, s);
     }
 }
 
@@ -354,7 +386,7 @@ static size_t bwd_lds_dd(const Dims& d) {
 
 bool bwd_supported(const Dims& d) {
     return d.nqz * d.nw <= 2 * kBwdThreads && d.norb * d.norb <= kBwdThreads && bwd_lds_dg(d) <= 160 * 1024 &&
-           bwd_lds_dd(d) <= 160 * 1024 && d.na * d.nb <= INT32_MAX;
+           bwd_lds_dd(d) <= 160 * 1024 && d.na * d.nb <= INT32_MAX && (d.na + 7) / 8 * 8 * d.nkz <= INT32_MAX;
 }
 
 hipError_t launch_bwd(const Dims& d, const double* G, const double* D, const double* A, const int32_t* nbr, cd alpha,
@@ -376,10 +408,19 @@ hipError_t launch_bwd(const Dims& d, const double* G, const double* D, const dou
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(bwd_dg_dh_kernel),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(bwd_dg_dh_kernel, dim3((unsigned)d.na), dim3(kBwdThreads), lds, stream, d, G, D, A, gS, calpha,
-                           offset, edges, dG, dA);
+        double* dApart = dA ? reinterpret_cast<double*>(reinterpret_cast<char*>(ws) + bwd_csr_bytes(d)) : nullptr;
+        const int64_t groups = (d.na + 7) / 8 * 8 * d.nkz;
+        hipLaunchKernelGGL(bwd_dg_dh_kernel, dim3((unsigned)groups), dim3(kBwdThreads), lds, stream, d, G, D, A, gS,
+                           calpha, offset, edges, dG, dApart);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
+        if (dA) {
+            const int64_t n = d.na * d.nb * 3 * d.norb * d.norb;
+            const unsigned g3 = (unsigned)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+            hipLaunchKernelGGL(bwd_dh_reduce_kernel, dim3(g3), dim3(256), 0, stream, d, nbr, dApart, dA);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
     }
     if (dD && pse_mfma_specialised(d)) return launch_dd_mfma(d, G, A, nbr, gS, calpha, dD, stream);
     if (dD) {

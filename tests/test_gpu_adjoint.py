@@ -57,6 +57,33 @@ def test_backward_matches_oracle(dims, seed):
     assert torch.count_nonzero(dG[:, :, :, 1:]) == 0
 
 
+@pytest.mark.parametrize("dims,seed", [SMALL[1], SMALL[2]], ids=["norb10", "odd_nb"])
+def test_out_of_range_neighbour_has_no_terms(dims, seed):
+    """An entry of nbr outside [0, na) contributes no terms: the gradients equal
+    the oracle's for a valid neighbour whose D coefficients are zero, and the
+    grad H gradient of that edge is exactly zero (every output is written)."""
+    inp = _rand(dims, seed + 40)
+    gS = _gS(inp["W"])
+    bad = inp["nbr"].copy()
+    bad[2, 1] = dims.na + 3
+    t = {k: torch.from_numpy(v).cuda() for k, v in inp.items()}
+    dG, dD, ddH = sse.backward(t["G"], t["D"], t["dH"], torch.from_numpy(bad).cuda(), torch.from_numpy(gS).cuda())
+    Dz = inp["D"].copy()
+    Dz[:, :, 2, 1] = 0
+    rG, rD, rH = oracle.sse_backward(dims, inp["G"], Dz, inp["dH"], inp["nbr"], gS)
+    ddH = ddH.cpu().numpy()
+    assert np.array_equal(ddH[2, 1], np.zeros_like(ddH[2, 1]))
+    assert _rel(dG.cpu().numpy(), rG) <= 1e-12
+    assert _rel(ddH, rH) <= 1e-12
+    keep = np.ones(dims.nb, dtype=bool)
+    keep[1] = False
+    dD = dD.cpu().numpy()
+    assert _rel(dD[:, :, 2][:, :, keep], rD[:, :, 2][:, :, keep]) <= 1e-12
+    others = [a for a in range(dims.na) if a != 2]
+    assert _rel(dD[:, :, others], rD[:, :, others]) <= 1e-12
+    assert np.isfinite(dD).all()
+
+
 def test_backward_skips_null_outputs_and_is_deterministic():
     d = SMALL[1][0]
     inp = _rand(d, 3)
