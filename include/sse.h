@@ -168,7 +168,12 @@ int sse_forward_signed(const sse_dims* dims, const double* G, const double* Dp, 
  *   dD[q,w-1,a,n,i,j] += conj(alpha) sum_{r,c} conj((A_i B A_j^H)[r,c]) g[r,c]
  *   ddH[a,n,i]        += conj(alpha d) g A_j B^H
  *   ddH[a,n,j]        += alpha d g^H A_i B
- * Shifted G blocks are re-gathered, not stored.
+ * Shifted G blocks are re-gathered, not stored.  The workspace
+ * (sse_workspace_bytes(dims, 0, 1) bytes) holds the reverse neighbour
+ * adjacency and, per momentum kz', every edge's share of dL/d(dH)
+ * (16 * nkz * na * nb * 3 * norb^2 bytes), added in kz' order, so results are
+ * bitwise reproducible.  An entry of nbr outside [0, na) has no terms: its
+ * ddH block is zero.
  */
 int sse_backward(const sse_dims* dims, const double* G, const double* D, const double* dH,
                  const int32_t* nbr, double alpha_re, double alpha_im, const double* dSigma,
