@@ -125,3 +125,14 @@ def test_signed_forward_rejects_bad_input(lib):
         assert lib.sse_forward_signed(ctypes.byref(good), *ptrs, 0.0, 1.0, 0, P(1), None, 0, None) == _lib.SSE_ERR_NULL
     assert lib.sse_forward_signed(ctypes.byref(good), *args()[:5], 0.0, 1.0, 0, None, None, 0, None) == _lib.SSE_ERR_NULL
     assert lib.sse_forward_signed(ctypes.byref(good), *args()[:5], 0.0, 1.0, 9, P(1), None, 0, None) == _lib.SSE_ERR_PRECISION
+
+
+def test_signed_forward_reduced_precision_needs_matrix_core_shape(lib):
+    """Shapes without a matrix-core kernel run in fp64 only: a reduced precision
+    is rejected before any launch (fake pointers are never dereferenced)."""
+    P = ctypes.c_void_p
+    generic = _lib.SSEDims(3, 11, 3, 4, 6, 3, 5, 2)
+    for prec in (1, 2):
+        rc = lib.sse_forward_signed(ctypes.byref(generic), *[P(1)] * 5, 0.0, 1.0, prec, P(1), None, 0, None)
+        assert rc == _lib.SSE_ERR_PRECISION
+        assert b"precision" in lib.sse_last_error()
