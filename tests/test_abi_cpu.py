@@ -133,6 +133,6 @@ def test_signed_forward_reduced_precision_needs_matrix_core_shape(lib):
     P = ctypes.c_void_p
     generic = _lib.SSEDims(3, 11, 3, 4, 6, 3, 5, 2)
     for prec in (1, 2):
-        rc = lib.sse_forward_signed(ctypes.byref(generic), *[P(1)] * 5, 0.0, 1.0, prec, P(1), None, 0, None)
+        rc = lib.sse_forward_signed(ctypes.byref(generic), *[P(1)] * 5, 0.0, 1.0, prec, P(1), P(1), 256, None)
         assert rc == _lib.SSE_ERR_PRECISION
         assert b"precision" in lib.sse_last_error()
