@@ -193,6 +193,10 @@ struct Fwd64 {
     static constexpr int PNC = 3 * NORB;
     static constexpr int PNT = (PNC + 15) / 16;
     static constexpr int NPT = 2 * PMT * PNT;     // P tiles per chunk
+    // issue cost of one P tile in main-GEMM k-steps: the same instruction time
+    // for fp64 and fp32; for fp16x2 its fp32 k-steps take twice an f16 k-step
+    // and the hi/lo split of its results about as much again
+    static constexpr int PTILE_COST = PREC == SSE_FP16X2 ? 3 * PKS : PKS;
     static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
     static_assert(X_IPW <= 64, "one item per lane");
     static_assert(NPT <= 32, "P tiles fit a 32-bit wave mask");
@@ -201,7 +205,7 @@ struct Fwd64 {
 };
 
 // Static deal of the P tiles of a chunk to waves: each tile goes to a wave on
-// the SIMD with the least matrix work so far (the two waves of SIMD s are s
+// the SIMD with the least issue time so far (the two waves of SIMD s are s
 // and s + 4), ties to the wave with fewer tiles.
 template <class C>
 struct PTileDeal {
@@ -218,7 +222,7 @@ struct PTileDeal {
                 const int lw = simd_load[w % 4], lb = simd_load[best % 4];
                 if (lw < lb || (lw == lb && count[w] < count[best])) best = w;
             }
-            simd_load[best % 4] += C::PKS;
+            simd_load[best % 4] += C::PTILE_COST;
             mask[best] |= 1u << t;
             ++count[best];
         }
