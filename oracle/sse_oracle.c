@@ -115,7 +115,7 @@ static void acc_mul_adj(int64_t N, cplx d, const cplx* T, const double* Y, cplx*
 /* One output block Sigma[k,e,a] (Eq. 3), written to out as N*N complex.
  * Eq. 3 integrates over signed frequencies; with the Nw stored frequencies
  * w_m > 0 the s = +1 terms (G at e - m) carry the coefficient at +w_m (Dp) and
- * the s = -1 terms (G at e + m) the coefficient at -w_m (Dm).  The north-star
+ * the s = -1 terms (G at e + m) the coefficient at -w_m (Dm).  The one-table
  * form reads the same table for both (Dm == Dp). */
 static void sigma_block(const odims* d, const double* G, const double* Dp, const double* Dm, const double* A,
                         const int32_t* nbr, cplx alpha, int64_t k, int64_t e, int64_t a,
@@ -194,7 +194,7 @@ int oracle_sse_points_signed(const int64_t* dims, const double* G, const double*
     return fail ? 7 : 0;
 }
 
-/* The spec form: one coefficient table for both signs of the frequency. */
+/* The one-table form: the same coefficient table for both signs of the frequency. */
 int oracle_sse_points(const int64_t* dims, const double* G, const double* D, const double* A,
                       const int32_t* nbr, double alpha_re, double alpha_im, int64_t npts,
                       const int64_t* pts, double* out) {
@@ -234,7 +234,7 @@ int oracle_sse_forward_signed(const int64_t* dims, const double* G, const double
     return fail ? 7 : 0;
 }
 
-/* Full Sigma, spec form (one table for both signs of the frequency). */
+/* Full Sigma, one-table form (the same table for both signs of the frequency). */
 int oracle_sse_forward(const int64_t* dims, const double* G, const double* D, const double* A,
                        const int32_t* nbr, double alpha_re, double alpha_im, double* Sigma) {
     return oracle_sse_forward_signed(dims, G, D, D, A, nbr, alpha_re, alpha_im, Sigma);

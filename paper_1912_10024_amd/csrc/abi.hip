@@ -104,7 +104,7 @@ int sse_effective_flops(const sse_dims* dims, double* f_eff) {
 namespace {
 
 // Sigma with the terms whose G sits at E - w reading Dp and those at E + w
-// reading Dm (the same table for the spec form)
+// reading Dm (the same table for sse_forward)
 int forward_impl(const sse_dims* dims, const double* G, const double* Dp, const double* Dm, const double* dH,
                  const int32_t* nbr, double alpha_re, double alpha_im, int precision, double* Sigma, void* workspace,
                  size_t workspace_bytes, void* stream) {

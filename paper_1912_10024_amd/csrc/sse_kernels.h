@@ -13,7 +13,7 @@ constexpr int kAccumulate = 4;   // Sigma += result instead of Sigma = result
 
 // direct term-by-term fp64 forward (any shape with norb^2 <= 1024); the terms
 // with G at E - w read Dp, those with G at E + w read Dm (Dm == Dp: the
-// spec form)
+// one-table form of sse_forward)
 bool generic_supported(const Dims& d);
 hipError_t launch_fwd_generic(const Dims& d, const double* G, const double* Dp, const double* Dm, const double* A,
                               const int32_t* nbr, cd alpha, double* S, hipStream_t stream);

@@ -5,7 +5,7 @@ that do not come from the oracle:
     which branch reads which table, and the energy offsets of both;
   * energy reversal: reversing the energy axis of G and swapping the two tables
     reverses the energy axis of Sigma (a swapped branch breaks it);
-  * linearity in each table separately, and the reduction to the north-star
+  * linearity in each table separately, and the reduction to the one-table
     form when both tables are equal;
   * term-by-term brute force in plain Python loops on a tiny case.
 """
@@ -76,7 +76,7 @@ def test_energy_reversal_swaps_the_tables(oracle_lib):
     assert _rel(Snot[:, ::-1], S) > 1e-2
 
 
-def test_linearity_in_each_table_and_north_star_reduction(oracle_lib):
+def test_linearity_in_each_table_and_one_table_reduction(oracle_lib):
     d = SMALL
     G, Dp, Dm, A, nbr = _rand(d, 4)
     Z = np.zeros_like(Dp)
