@@ -125,7 +125,8 @@ def sampled_error(S, pts, ref):
 
 
 def phonon_sample_error(d, Gs, Go, dH, nbr, P, seed=11):
-    """Relative error of sampled Pi blocks against the CPU oracle."""
+    """Relative error of sampled Pi blocks against the CPU oracle.  Part of the
+    CPU-oracle leg: it runs only with the CPU baseline (not with --no-cpu)."""
     import torch
     from oracle import oracle
     from paper_1912_10024_amd.inputs import Dims
