@@ -39,7 +39,7 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--config", default="device", choices=["tiny", "mid", "device"])
-    p.add_argument("--forms", default="fp64,fp32,fp16x2",
+    p.add_argument("--forms", default="fp64,fp32,bf16x2,fp16x2",
                    help="comma-separated operand precisions to time; the first is the headline value")
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle baseline sample")
     p.add_argument("--no-cpu", action="store_true")
@@ -332,9 +332,9 @@ def main():
         f_block = f_eff / (d.nkz * d.ne * d.na)
         cpu, cpu_pts, cpu_ref = cpu_baseline(d, G, D, dH, nbr, args.cpu_seconds, f_block)
     gemm = flops.pd_mfma_flops(d)
-    peaks = {"fp64": FP64_MFMA_PEAK, "fp32": FP32_MFMA_PEAK, "fp16x2": FP16_MFMA_PEAK}
-    # fp16x2: the four hi/lo partial products of the P.D GEMM on the fp16 matrix cores
-    mfma_flops = {"fp64": gemm, "fp32": gemm, "fp16x2": 4 * flops.pd_gemm_flops(d)}
+    peaks = {"fp64": FP64_MFMA_PEAK, "fp32": FP32_MFMA_PEAK, "bf16x2": FP16_MFMA_PEAK, "fp16x2": FP16_MFMA_PEAK}
+    # 16-bit hi/lo forms: the four partial products of the P.D GEMM on the 16-bit matrix cores
+    mfma_flops = {"fp64": gemm, "fp32": gemm, "bf16x2": 4 * flops.pd_gemm_flops(d), "fp16x2": 4 * flops.pd_gemm_flops(d)}
     res = {}
     for form in forms:
         S = torch.empty(d.sigma_shape, dtype=torch.complex128, device=dev)
@@ -351,7 +351,8 @@ def main():
                          "unit": "TFLOP/s", "frac": round(achieved / peaks[form], 4), "traffic": None,
                          "flops_per_launch": mfma_flops[form],
                          "what": (f"useful {form} matrix-core flops: P.D GEMM + P = X.gradH^H products"
-                                  if form != "fp16x2" else "fp16 matrix-core flops of the P.D GEMM (4 hi/lo products)")},
+                                  if form in ("fp64", "fp32") else
+                                  "16-bit matrix-core flops of the P.D GEMM (4 hi/lo products)")},
         }
         if cpu is not None:
             res[form]["err"] = sampled_error(S, cpu_pts, cpu_ref)

@@ -66,7 +66,7 @@
 extern "C" {
 #endif
 
-#define SSE_ABI_VERSION 2
+#define SSE_ABI_VERSION 3
 
 typedef struct sse_dims {
     int64_t nkz;     /* electron momentum points kz (periodic grid)              */
@@ -84,7 +84,15 @@ enum sse_precision {
     SSE_FP32 = 1,    /* operands of the dense products rounded to fp32 after the fp64
                         gather, fp32 matrix cores, each 36-term K chunk accumulated in
                         fp32 then added in fp64; fp64 (qz, w, +/-) reduction            */
-    SSE_FP16X2 = 2   /* half precision with compensation (Sec. "Mixed-Precision
+    SSE_BF16X2 = 2,  /* every operand of the dense product split into bfloat16 hi + lo
+                        (hi = bf16(x), lo = bf16(x - hi); bf16 has the exponent range of
+                        fp32, so no scaling), the four partial products on the bf16
+                        matrix cores, fp32 accumulation per K chunk, fp64 (qz, w, +/-)
+                        reduction.  About 16 significant bits per operand: expect
+                        relative errors near 1e-5                                        */
+    SSE_BF16X3 = 3,  /* three-term bfloat16 split (24 significant bits); declared for
+                        the interface, not built: every call returns SSE_ERR_PRECISION    */
+    SSE_FP16X2 = 4   /* half precision with compensation (Sec. "Mixed-Precision
                         Computation"): D, grad H and the left products normalised
                         by powers of two (per atom; per K chunk and source energy),
                         every operand of the dense product split into fp16 hi + lo,

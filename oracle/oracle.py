@@ -11,6 +11,7 @@ layouts.
 from __future__ import annotations
 
 import ctypes
+import hashlib
 import os
 import subprocess
 
@@ -30,7 +31,23 @@ def build(verbose: bool = False, src: str = SRC, out: str = LIB) -> str:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
     os.replace(out + ".tmp", out)
+    with open(out + ".sha256", "w") as fh:
+        fh.write(_source_hash(src) + "\n")
     return out
+
+
+def _source_hash(src: str = SRC) -> str:
+    with open(src, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def _stale(src: str = SRC, out: str = LIB) -> bool:
+    """True if the library is missing or was built from another version of the source."""
+    stamp = out + ".sha256"
+    if not (os.path.exists(out) and os.path.exists(stamp)):
+        return True
+    with open(stamp) as fh:
+        return fh.read().strip() != _source_hash(src)
 
 
 def _open(path):
@@ -52,10 +69,17 @@ def _open(path):
     return lib
 
 
+def current_lib_path() -> str:
+    """Path of a liboracle.so built from the current sse_oracle.c (rebuilt if stale)."""
+    if _stale():
+        build()
+    return LIB
+
+
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
+        if _stale():
             build()
         _lib = _open(LIB)
     return _lib

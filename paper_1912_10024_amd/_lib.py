@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsse.so")
 
 SSE_OK, SSE_ERR_NULL, SSE_ERR_DIMS, SSE_ERR_WORKSPACE, SSE_ERR_PRECISION, SSE_ERR_HIP, SSE_ERR_NBR = range(7)
-PRECISIONS = {"fp64": 0, "fp32": 1, "fp16x2": 2}
+# the sse_precision codes of include/sse.h ("bf16x3" is declared there but not built)
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x2": 2, "bf16x3": 3, "fp16x2": 4}
 EXPORTS = ("sse_abi_version", "sse_last_error", "sse_workspace_bytes", "sse_effective_flops",
            "sse_forward", "sse_forward_signed", "sse_backward", "sse_check_nbr", "sse_combine_d",
            "sse_phonon_forward")
@@ -32,6 +33,13 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1912_10024_amd.build`")
+    from . import build as _build
+
+    stamp = LIB_PATH + ".sha256"
+    recorded = open(stamp).read().strip() if os.path.exists(stamp) else None
+    if recorded != _build.source_hash():
+        raise RuntimeError(f"{LIB_PATH} was not built from the current sources (recorded source hash {recorded!r}); "
+                           "rebuild it with `python -m paper_1912_10024_amd.build`")
     lib = ctypes.CDLL(LIB_PATH)
     P, D, I64, SZ = ctypes.c_void_p, ctypes.c_double, ctypes.c_int64, ctypes.c_size_t
     DP = ctypes.POINTER(SSEDims)

@@ -2,6 +2,7 @@
 from __future__ import annotations
 
 import glob
+import hashlib
 import os
 import subprocess
 import sys
@@ -23,6 +24,21 @@ def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
+def source_files():
+    """Every file the library is built from (kernels, their headers, the ABI header)."""
+    return sources() + sorted(glob.glob(os.path.join(HERE, "csrc", "*.h"))) + [os.path.join(ROOT, "include", "sse.h")]
+
+
+def source_hash() -> str:
+    """sha256 over the sources, recorded next to the library when it is built."""
+    h = hashlib.sha256()
+    for f in source_files():
+        h.update(os.path.relpath(f, ROOT).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def build(verbose: bool = False, extra=()) -> str:
     cmd = [HIPCC, *FLAGS, *extra, "-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(HERE, "csrc"),
            *sources(), "-o", LIB + ".tmp"]
@@ -34,7 +50,10 @@ def build(verbose: bool = False, extra=()) -> str:
         raise RuntimeError(f"hipcc failed ({res.returncode}):\n{msgs}")
     if verbose and msgs.strip():
         print(msgs)
+    digest = source_hash()
     os.replace(LIB + ".tmp", LIB)
+    with open(LIB + ".sha256", "w") as fh:
+        fh.write(digest + "\n")
     return LIB
 
 

@@ -61,6 +61,22 @@ int hip_fail(hipError_t e, const char* what) {
     return fail(SSE_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+bool precision_known(int p) {
+    return p == SSE_FP64 || p == SSE_FP32 || p == SSE_BF16X2 || p == SSE_BF16X3 || p == SSE_FP16X2;
+}
+
+// precision check of the forward entry points: unknown codes, and the declared
+// form without a kernel, are SSE_ERR_PRECISION
+int check_precision(int p) {
+    if (!precision_known(p)) return fail(SSE_ERR_PRECISION, "unknown precision %d", p);
+    if (p == SSE_BF16X3)
+        return fail(SSE_ERR_PRECISION,
+                    "precision SSE_BF16X3 (three-term bfloat16 split) is not built: its operands take 12 bytes per "
+                    "K element, more than the matrix-core kernel's LDS holds; use SSE_FP16X2 or SSE_FP32 for errors "
+                    "below 1e-6");
+    return SSE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -73,8 +89,7 @@ int sse_workspace_bytes(const sse_dims* dims, int precision, int backward, size_
     int rc = check_dims(dims);
     if (rc) return rc;
     if (!bytes) return fail(SSE_ERR_NULL, "bytes is NULL");
-    if (backward == 0 && precision != SSE_FP64 && precision != SSE_FP32 && precision != SSE_FP16X2)
-        return fail(SSE_ERR_PRECISION, "unknown precision %d", precision);
+    if (backward == 0 && !precision_known(precision)) return fail(SSE_ERR_PRECISION, "unknown precision %d", precision);
     if (backward < 0 || backward > 2) return fail(SSE_ERR_DIMS, "op must be 0 (forward), 1 (backward) or 2 (combine_d)");
     size_t ws = 256;  // status flag of sse_check_nbr
     if (backward == 1) {
@@ -111,8 +126,7 @@ int forward_impl(const sse_dims* dims, const double* G, const double* Dp, const 
     int rc = check_dims(dims);
     if (rc) return rc;
     if (!G || !Dp || !Dm || !dH || !nbr || !Sigma) return fail(SSE_ERR_NULL, "a tensor pointer is NULL");
-    if (precision != SSE_FP64 && precision != SSE_FP32 && precision != SSE_FP16X2)
-        return fail(SSE_ERR_PRECISION, "unknown precision %d", precision);
+    if ((rc = check_precision(precision))) return rc;
     size_t need = 0;
     sse_workspace_bytes(dims, precision, 0, &need);
     if (need > 0 && (workspace == nullptr || workspace_bytes < need))

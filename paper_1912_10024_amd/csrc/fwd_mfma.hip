@@ -1,5 +1,5 @@
 // Matrix-core forward kernel of the scattering self-energy (Eq. 3), with fp64,
-// fp32 and fp16 hi/lo GEMM operands.
+// fp32, and fp16 or bfloat16 hi/lo GEMM operands.
 //
 // Regrouping (the fission of Sec. "Dataflow Optimizations", taken one step
 // further so the matrix cores see one dense GEMM per atom):
@@ -67,40 +67,65 @@ struct Oper<SSE_FP32> {
 };
 
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-// fp16 hi/lo form: a value x (already scaled into the fp16 range) is split as
-// x ~ hi + lo with hi = fp16(x), lo = fp16(x - hi), leaving a relative error of
-// about 2^-22.  One K element of the GEMM is four fp16 values, (hi, hi, lo, lo)
-// on the A side and (hi, lo, hi, lo) on the B side, so one 16x16x16 f16 MFMA
-// step sums hi.hi + hi.lo + lo.hi + lo.lo over four K elements; the products
-// are exact in fp32 and accumulate in fp32.
+// 16-bit hi/lo forms: a value x is split as x ~ hi + lo with hi = r(x) and
+// lo = r(x - hi) for the 16-bit rounding r (fp16 after power-of-two
+// normalisation, or bfloat16, whose exponent range is fp32's).  One K element
+// of the GEMM is four 16-bit values, (hi, hi, lo, lo) on the A side and
+// (hi, lo, hi, lo) on the B side, so one 16x16x16 MFMA step sums hi.hi + hi.lo
+// + lo.hi + lo.lo over four K elements; the products are exact in fp32 and
+// accumulate in fp32.  fp16 keeps 22 significant bits per operand, bfloat16 16.
+template <class V>
+__device__ __forceinline__ V neg_halves(V x, bool neg) {
+    u32x2 v = __builtin_bit_cast(u32x2, x);
+    const unsigned m = neg ? 0x80008000u : 0u;
+    v.x ^= m;
+    v.y ^= m;
+    return __builtin_bit_cast(V, v);
+}
 template <>
 struct Oper<SSE_FP16X2> {
     using T = h4;
     using Acc = f32x4;
     static __device__ __forceinline__ Acc mma(T a, T b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0); }
-    static __device__ __forceinline__ T neg_if(T x, bool neg) {
-        u32x2 v = __builtin_bit_cast(u32x2, x);
-        const unsigned m = neg ? 0x80008000u : 0u;
-        v.x ^= m;
-        v.y ^= m;
-        return __builtin_bit_cast(T, v);
-    }
+    static __device__ __forceinline__ T neg_if(T x, bool neg) { return neg_halves(x, neg); }
     // the fp32 accumulator layout of the 16x16 f32 MFMAs
     static __device__ __forceinline__ int row_of(int lane, int v) { return 4 * (lane >> 4) + v; }
+    // (hi, lo) of x as one 32-bit word, hi in the low half
+    static __device__ __forceinline__ unsigned split_word(float x) {
+        const _Float16 h = (_Float16)x;
+        const _Float16 l = (_Float16)(x - (float)h);
+        typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+        return __builtin_bit_cast(unsigned, h2{h, l});
+    }
+    static __device__ __forceinline__ T split_a(double x) {
+        const _Float16 h = (_Float16)(float)x;
+        const _Float16 l = (_Float16)(float)(x - (double)h);
+        return h4{h, h, l, l};
+    }
 };
-__device__ __forceinline__ h4 split_a(double x) {
-    const _Float16 h = (_Float16)(float)x;
-    const _Float16 l = (_Float16)(float)(x - (double)h);
-    return h4{h, h, l, l};
-}
-// (hi, lo) as one 32-bit word; the B entry (hi, lo, hi, lo) is that word twice
-__device__ __forceinline__ unsigned split_b_word(float x) {
-    const _Float16 h = (_Float16)x;
-    const _Float16 l = (_Float16)(x - (float)h);
-    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
-    return __builtin_bit_cast(unsigned, h2{h, l});
-}
+template <>
+struct Oper<SSE_BF16X2> {
+    using T = s4;  // four bfloat16 bit patterns
+    using Acc = f32x4;
+    static __device__ __forceinline__ Acc mma(T a, T b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0); }
+    static __device__ __forceinline__ T neg_if(T x, bool neg) { return neg_halves(x, neg); }
+    static __device__ __forceinline__ int row_of(int lane, int v) { return 4 * (lane >> 4) + v; }
+    static __device__ __forceinline__ unsigned short bits(__bf16 h) { return __builtin_bit_cast(unsigned short, h); }
+    static __device__ __forceinline__ float value(__bf16 h) { return (float)h; }
+    static __device__ __forceinline__ unsigned split_word(float x) {
+        const __bf16 h = (__bf16)x;               // round to nearest even
+        const __bf16 l = (__bf16)(x - value(h));  // x - hi is exact in fp32
+        return (unsigned)bits(h) | ((unsigned)bits(l) << 16);
+    }
+    static __device__ __forceinline__ T split_a(double x) {
+        const __bf16 h = (__bf16)(float)x;
+        const __bf16 l = (__bf16)(float)(x - (double)value(h));
+        const short hs = (short)bits(h), ls = (short)bits(l);
+        return s4{hs, hs, ls, ls};
+    }
+};
 // power of two s with m * s in [2^(t-1), 2^t) (1 for m = 0)
 __device__ __forceinline__ double pow2_scale(double m, int t) {
     if (!(m > 0.0)) return 1.0;
@@ -193,10 +218,13 @@ struct Fwd64 {
     static constexpr int PNC = 3 * NORB;
     static constexpr int PNT = (PNC + 15) / 16;
     static constexpr int NPT = 2 * PMT * PNT;     // P tiles per chunk
+    // 16-bit hi/lo operand forms, and the one of them that normalises by powers of two
+    static constexpr bool SPLIT = PREC == SSE_FP16X2 || PREC == SSE_BF16X2;
+    static constexpr bool NORM = PREC == SSE_FP16X2;
     // issue cost of one P tile in main-GEMM k-steps: the same instruction time
-    // for fp64 and fp32; for fp16x2 its fp32 k-steps take twice an f16 k-step
-    // and the hi/lo split of its results about as much again
-    static constexpr int PTILE_COST = PREC == SSE_FP16X2 ? 3 * PKS : PKS;
+    // for fp64 and fp32; for the 16-bit forms its fp32 k-steps take twice a
+    // 16-bit k-step and the hi/lo split of its results about as much again
+    static constexpr int PTILE_COST = SPLIT ? 3 * PKS : PKS;
     static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
     static_assert(X_IPW <= 64, "one item per lane");
     static_assert(NPT <= 32, "P tiles fit a 32-bit wave mask");
@@ -294,8 +322,8 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     TP* sX = reinterpret_cast<TP*>(sA + C::L_A + C::L_AP);
     double* sR = sA + C::L_A + C::L_AP + C::L_X;
     double* sS = sR + C::L_R;
-    constexpr bool F16 = PREC == SSE_FP16X2;
-    static_assert(!F16 || EB == C::WAVES, "fp16 form: wave w forms the X rows of source energy w");
+    constexpr bool NORM = C::NORM, SPLIT = C::SPLIT;
+    static_assert(!NORM || EB == C::WAVES, "fp16 form: wave w forms the X rows of source energy w");
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -310,7 +338,7 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     // fp16 form: per-atom power-of-two normalisation of D (largest part below
     // 2^7) and of grad H (below 2); workgroup max of the parts first
     double sc_d = 1.0, sc_h = 1.0, inv_base = 1.0;
-    if constexpr (F16) {
+    if constexpr (NORM) {
         auto block_max = [&](double m) {
             for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
             __syncthreads();
@@ -343,9 +371,9 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
         const int ij = x % 9, n = (x / 9) % NB, w = (x / (9 * NB)) % NW, q = x / (9 * NB * NW);
         const cd v = cload(Dg, off_D(d, q, w, a, n) + ij);
         T* o = sD + q * C::QS + w * C::WS + n * 18 + ij * 2;
-        if constexpr (F16) {
-            o[0] = split_a(v.re * sc_d);
-            o[1] = split_a(v.im * sc_d);
+        if constexpr (SPLIT) {
+            o[0] = O::split_a(v.re * sc_d);
+            o[1] = O::split_a(v.im * sc_d);
         } else {
             o[0] = T(v.re);
             o[1] = T(v.im);
@@ -418,14 +446,14 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     // 2^14); the inverse of all scale factors of the chunk's column goes to LDS
     constexpr int XT = 14 - ceil_log2(4 * NORB);
     auto finish_x = [&](int g) {
-        if (g >= niter || (!F16 && !x_lane)) return;
+        if (g >= niter || (!NORM && !x_lane)) return;
         const int np = (g % C::NCHUNK) % C::NP;
         const double* Ar = sA + np * C::PSTR + (x_nl * 3 + x_i) * C::NNS + r * C::AR;
         cd acc{0.0, 0.0};
 #pragma unroll
         for (int t = 0; t < NORB; ++t) cfma(acc, cd{Ar[2 * t], Ar[2 * t + 1]}, gv[t]);
         if (!g_ok) acc = cd{0.0, 0.0};
-        if constexpr (F16) {
+        if constexpr (NORM) {
             const double m = fmax(fabs(acc.re), fabs(acc.im));
             int e = -4000;
             if (m > 0.0) frexp(m, &e);
@@ -522,9 +550,9 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
             if constexpr (PREC != SSE_FP64) acc += acc1[t];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                if constexpr (F16) {
+                if constexpr (SPLIT) {
                     unsigned* q = reinterpret_cast<unsigned*>(P + pt_out[s0 + t][v]);
-                    const unsigned w = split_b_word(acc[v]);
+                    const unsigned w = O::split_word(acc[v]);
                     q[0] = w;
                     q[1] = w;
                 } else
@@ -626,7 +654,7 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
                 if (has_extra) part_x = O::mma(b, bx[cur], ks == 0 ? zero_acc : part_x);
             }
         }
-        if constexpr (F16) {
+        if constexpr (NORM) {
             // undo the chunk's normalisation of the lane's column (source energy)
             const double* inv = sS + (g & 3) * EB;
             auto el_of = [&](int nt) {
@@ -766,13 +794,11 @@ static hipError_t launch_fwd_flags(const Dims& d, const double* G, const double*
                                    const int32_t* nbr, cd alpha, double* S, hipStream_t stream) {
     using C = Fwd64<NORB, NKZ, NW, NB, EB, PREC>;
     auto kern = fwd_mfma_kernel<NORB, NKZ, NW, NB, EB, PREC, FLAGS>;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)C::LDS_BYTES);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    // set on every launch (cheap): the attribute is per device, and a process-wide
+    // flag would race between host threads
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)C::LDS_BYTES);
+    if (e != hipSuccess) return e;
     const int64_t groups = ((d.na + 7) / 8) * 8 * NORB;
     hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(C::THREADS), C::LDS_BYTES, stream, d, G, D, A, nbr, alpha, S);
     return hipGetLastError();
@@ -815,6 +841,7 @@ hipError_t launch_fwd_mfma(const Dims& d, int precision, const double* G, const 
     if (precision == SSE_FP64) return dispatch_fwd<SSE_FP64>(d, G, D, A, nbr, alpha, S, stream, flags);
     if (precision == SSE_FP32) return dispatch_fwd<SSE_FP32>(d, G, D, A, nbr, alpha, S, stream, flags);
     if (precision == SSE_FP16X2) return dispatch_fwd<SSE_FP16X2>(d, G, D, A, nbr, alpha, S, stream, flags);
+    if (precision == SSE_BF16X2) return dispatch_fwd<SSE_BF16X2>(d, G, D, A, nbr, alpha, S, stream, flags);
     return hipErrorInvalidValue;
 }
 

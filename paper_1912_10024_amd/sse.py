@@ -32,7 +32,16 @@ def dims_of(G: torch.Tensor, D: torch.Tensor, dH: torch.Tensor, nbr: torch.Tenso
     return d
 
 
+def _resolved(t: torch.Tensor) -> torch.Tensor:
+    """The tensor with PyTorch's lazy conjugate and negative bits applied, so its
+    memory holds the values it stands for (a .conj() view shares its base's
+    memory and would otherwise be read unconjugated)."""
+    return t.resolve_conj().resolve_neg() if t is not None else None
+
+
 def _check_tensor(t: torch.Tensor, name: str, dtype=torch.complex128):
+    if t.is_conj() or t.is_neg():
+        raise ValueError(f"{name} carries a lazy conjugate/negative bit; resolve it first")
     if t.dtype != dtype:
         raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
     if t.device.type != "cuda":
@@ -86,6 +95,7 @@ def check_nbr(nbr: torch.Tensor, na: int) -> None:
 def combine_d(Dfull: torch.Tensor, nbr: torch.Tensor) -> torch.Tensor:
     """Eq. 3 bracket D_ba - D_bb - D_aa + D_ab per neighbour slot from the
     [nqz, nw, na, nb+1, 3, 3] phonon blocks; needs a symmetric neighbour table."""
+    Dfull = _resolved(Dfull)
     _check_tensor(Dfull, "Dfull")
     _check_tensor(nbr, "nbr", torch.int32)
     if Dfull.dim() != 6 or Dfull.shape[4:] != (3, 3) or Dfull.shape[3] != nbr.shape[1] + 1 or Dfull.shape[2] != nbr.shape[0]:
@@ -110,14 +120,19 @@ def forward_signed(G, Dp, Dm, dH, nbr, alpha=1j, precision: str = "fp64", out=No
     """Sigma of Eq. 3 over both signs of the frequency: the terms with G at
     E - w read Dp (coefficients at +w), those with G at E + w read Dm (at -w);
     both in D's layout.  Dm is Dp gives forward()."""
-    if Dm is not Dp:
-        _check_tensor(Dm, "Dm")
-        if Dm.shape != Dp.shape:
-            raise ValueError(f"Dm must have Dp's shape {tuple(Dp.shape)}")
+    if Dm is Dp:
+        return _forward(G, Dp, Dp, dH, nbr, alpha, precision, out, ws)
+    Dp, Dm = _resolved(Dp), _resolved(Dm)
+    _check_tensor(Dm, "Dm")
+    if Dm.shape != Dp.shape:
+        raise ValueError(f"Dm must have Dp's shape {tuple(Dp.shape)}")
     return _forward(G, Dp, Dm, dH, nbr, alpha, precision, out, ws)
 
 
 def _forward(G, D, Dm, dH, nbr, alpha, precision, out, ws) -> torch.Tensor:
+    same = Dm is D
+    G, D, dH = _resolved(G), _resolved(D), _resolved(dH)
+    Dm = D if same else Dm
     d = dims_of(G, D, dH, nbr)
     for t, n in ((G, "G"), (D, "D"), (dH, "dH")):
         _check_tensor(t, n)
@@ -135,7 +150,7 @@ def _forward(G, D, Dm, dH, nbr, alpha, precision, out, ws) -> torch.Tensor:
     lib = _lib.load()
     cd = _lib.SSEDims.of(d)
     a = complex(alpha)
-    if Dm is D:
+    if Dm is D or Dm.data_ptr() == D.data_ptr():
         rc = lib.sse_forward(ctypes.byref(cd), _ptr(G), _ptr(D), _ptr(dH), _ptr(nbr), a.real, a.imag,
                              PRECISIONS[precision], _ptr(out), _ptr(ws), ws.numel(), _stream(G.device))
         _raise(rc, "sse_forward")
@@ -152,6 +167,7 @@ def phonon_forward(Gs, Go, dH, nbr, nqz: int, nw: int, beta=-1j, out=None) -> to
     Gs is the electron Green's function of the same component as Pi, Go the
     opposite one (both [nkz, ne, na, slots, norb, norb]); beta carries -i and
     the energy quadrature weight."""
+    Gs, Go, dH = _resolved(Gs), _resolved(Go), _resolved(dH)
     if Gs.dim() != 6 or dH.dim() != 5 or nbr.dim() != 2:
         raise ValueError("expected Gs/Go[nkz,ne,na,slots,norb,norb], dH[na,nb,3,norb,norb], nbr[na,nb]")
     nkz, ne, na, gs, norb, _ = Gs.shape
@@ -180,6 +196,7 @@ def phonon_forward(Gs, Go, dH, nbr, nqz: int, nw: int, beta=-1j, out=None) -> to
 
 def backward(G, D, dH, nbr, dSigma, alpha=1j, need=(True, True, True), ws=None):
     """(dL/dG, dL/dD, dL/d dH) for dSigma = dL/dSigma (PyTorch complex-gradient convention)."""
+    G, D, dH, dSigma = _resolved(G), _resolved(D), _resolved(dH), _resolved(dSigma)
     d = dims_of(G, D, dH, nbr)
     for t, n in ((G, "G"), (D, "D"), (dH, "dH"), (dSigma, "dSigma")):
         _check_tensor(t, n)
@@ -217,7 +234,7 @@ class SSEFunction(torch.autograd.Function):
     def backward(ctx, gS):
         G, D, dH, nbr = ctx.saved_tensors
         need = ctx.needs_input_grad[:3]
-        dG, dD, ddH = backward(G, D, dH, nbr, gS.contiguous(), alpha=ctx.alpha, need=need)
+        dG, dD, ddH = backward(G, D, dH, nbr, _resolved(gS).contiguous(), alpha=ctx.alpha, need=need)
         return dG, dD, ddH, None, None
 
 

@@ -73,6 +73,24 @@ def test_bad_precision_rejected(lib):
     assert "precision" in lib.sse_last_error().decode()
 
 
+def test_precision_codes_match_the_interface():
+    """The header's sse_precision codes are the interface's (FP64 0, FP32 1,
+    BF16X2 2, BF16X3 3) plus FP16X2 4, and the binding uses the same codes."""
+    txt = open(os.path.join(ROOT, "include", "sse.h")).read()
+    enum = txt[txt.index("enum sse_precision"):txt.index("};", txt.index("enum sse_precision"))]
+    enum = re.sub(r"/\*.*?\*/", "", enum, flags=re.S)
+    codes = {m.group(1).lower(): int(m.group(2)) for m in re.finditer(r"SSE_(\w+)\s*=\s*(\d+)", enum)}
+    assert codes == {"fp64": 0, "fp32": 1, "bf16x2": 2, "bf16x3": 3, "fp16x2": 4}
+    assert codes == _lib.PRECISIONS
+
+
+def test_declared_but_unbuilt_precision_is_rejected(lib):
+    """SSE_BF16X3 is declared but has no kernel: a precision error before any
+    launch (the pointers here are never dereferenced)."""
+    assert _call_forward(lib, CONFIGS["tiny"], precision=_lib.PRECISIONS["bf16x3"]) == _lib.SSE_ERR_PRECISION
+    assert "not built" in lib.sse_last_error().decode()
+
+
 def test_workspace_too_small_rejected(lib):
     d = CONFIGS["mid"]
     need = ctypes.c_size_t(0)

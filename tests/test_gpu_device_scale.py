@@ -33,14 +33,14 @@ def _compact(d, G, D, dH, nbr, atoms):
 def device_problem():
     d = CONFIGS["device"]
     print(f"[gpu] device-scale inputs {d.as_tuple()}", flush=True)
-    inp = generate_device(d, CONFIG_INDEX["device"], device="cuda")
+    inp = generate_device(d, CONFIG_INDEX["device"], device="cuda", which=("nbr", "G<", "D<", "D>", "dH"))
     sse.check_nbr(inp["nbr"], d.na)
     yield d, inp
     del inp
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-6), ("fp16x2", 1e-6)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-6), ("bf16x2", 5e-5), ("fp16x2", 1e-6)])
 def test_device_scale_sampled_parity(device_problem, precision, tol):
     d, inp = device_problem
     G, D, dH, nbr = inp["G<"], inp["D<"], inp["dH"], inp["nbr"]
@@ -63,4 +63,37 @@ def test_device_scale_sampled_parity(device_problem, precision, tol):
     print(f"  {precision} device-scale sampled rel err {err:.3e} over {len(pts)} blocks", flush=True)
     assert err <= tol
     assert torch.isfinite(torch.view_as_real(S)).all()
+    del S
+
+
+def _sample(d, rng, atoms):
+    pts = []
+    for a in atoms:
+        for e in (0, 1, d.nw - 1, d.nw, d.ne // 2, d.ne - d.nw - 1, d.ne - 2, d.ne - 1):
+            pts.append((int(rng.integers(d.nkz)), e, a))
+        pts += [(int(rng.integers(d.nkz)), int(rng.integers(d.ne)), a) for _ in range(4)]
+    return pts
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp16x2", 1e-6)])
+def test_device_scale_signed_sampled_parity(device_problem, precision, tol):
+    """The signed-frequency form (D< for +w, D> standing in for the table at
+    -w) in the launch configuration it runs in at device scale."""
+    d, inp = device_problem
+    G, Dp, Dm, dH, nbr = inp["G<"], inp["D<"], inp["D>"], inp["dH"], inp["nbr"]
+    print(f"[gpu] device-scale signed forward {precision}", flush=True)
+    S = sse.forward_signed(G, Dp, Dm, dH, nbr, precision=precision)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(77)
+    atoms = [0, d.na - 1] + [int(x) for x in rng.choice(d.na, size=2, replace=False)]
+    sub, Gs, Dps, Hs, nbs, remap = _compact(d, G, Dp, dH, nbr, atoms)
+    idx_a = torch.tensor(sorted(remap, key=remap.get), device=G.device)
+    Dms = np.ascontiguousarray(Dm.index_select(2, idx_a).cpu().numpy())
+    pts = _sample(d, rng, atoms)
+    ref = oracle.sse_points_signed(sub, Gs, Dps, Dms, Hs, nbs, [(k, e, remap[a]) for k, e, a in pts])
+    idx = torch.tensor(pts, device=G.device)
+    got = S[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy()
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    print(f"  {precision} device-scale signed sampled rel err {err:.3e} over {len(pts)} blocks", flush=True)
+    assert err <= tol
     del S

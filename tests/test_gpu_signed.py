@@ -12,7 +12,7 @@ from paper_1912_10024_amd.inputs import CONFIGS, CONFIG_INDEX, Dims, anti_hermit
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-12, "fp32": 1e-6, "fp16x2": 1e-6}
+TOL = {"fp64": 1e-12, "fp32": 1e-6, "fp16x2": 1e-6, "bf16x2": 5e-5}
 
 
 def _rand(d: Dims, seed: int):
@@ -30,7 +30,7 @@ def _rel(x, y):
 
 
 SHAPES = [
-    (Dims(nkz=7, ne=21, nqz=7, nw=10, na=5, nb=4, norb=10, g_slots=1), 1, ("fp64", "fp32", "fp16x2")),  # matrix cores
+    (Dims(nkz=7, ne=21, nqz=7, nw=10, na=5, nb=4, norb=10, g_slots=1), 1, ("fp64", "fp32", "bf16x2", "fp16x2")),
     (Dims(nkz=7, ne=13, nqz=7, nw=10, na=4, nb=3, norb=10, g_slots=2), 2, ("fp64", "fp16x2")),          # nb 3
     (Dims(nkz=3, ne=19, nqz=3, nw=2, na=9, nb=4, norb=4, g_slots=1), 3, ("fp64", "fp32")),              # small instance
     (Dims(nkz=3, ne=11, nqz=3, nw=4, na=6, nb=3, norb=5, g_slots=2), 4, ("fp64",)),                      # vector-ALU kernel

@@ -58,7 +58,7 @@ def _pin_checks(lib):
 
 
 def test_unmutated_oracle_passes_all_pins():
-    assert _pin_checks(oracle.Bound(oracle.LIB if os.path.exists(oracle.LIB) else oracle.build())) == []
+    assert _pin_checks(oracle.Bound(oracle.current_lib_path())) == []
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
@@ -111,7 +111,7 @@ def _pse_pin_checks(lib):
 
 
 def test_unmutated_oracle_passes_pse_pins():
-    assert _pse_pin_checks(oracle.Bound(oracle.LIB if os.path.exists(oracle.LIB) else oracle.build())) == []
+    assert _pse_pin_checks(oracle.Bound(oracle.current_lib_path())) == []
 
 
 @pytest.mark.parametrize("name", sorted(PSE_MUTANTS))
