@@ -1,5 +1,5 @@
-// Matrix-core forward kernel of the scattering self-energy (Eq. 3), with fp64,
-// fp32, and fp16 or bfloat16 hi/lo GEMM operands.
+// Matrix-core forward kernel of the scattering self-energy (Eq. 3), with fp64 or
+// fp32 GEMM operands (the split 16-bit forms are in fwd_h16.hip).
 //
 // Regrouping (the fission of Sec. "Dataflow Optimizations", taken one step
 // further so the matrix cores see one dense GEMM per atom):
@@ -32,6 +32,7 @@
 // can receive no more contributions are scaled by alpha and written out.
 #include <type_traits>
 
+#include "fwd_common.h"
 #include "sse_kernels.h"
 
 namespace sse {
@@ -65,90 +66,6 @@ struct Oper<SSE_FP32> {
     // C[i][j] of a 16x16 tile sits in lane j + 16*(i/4), register i%4
     static __device__ __forceinline__ int row_of(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
-
-typedef _Float16 h4 __attribute__((ext_vector_type(4)));
-typedef short s4 __attribute__((ext_vector_type(4)));
-typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-// 16-bit hi/lo forms: a value x is split as x ~ hi + lo with hi = r(x) and
-// lo = r(x - hi) for the 16-bit rounding r (fp16 after power-of-two
-// normalisation, or bfloat16, whose exponent range is fp32's).  One K element
-// of the GEMM is four 16-bit values, (hi, hi, lo, lo) on the A side and
-// (hi, lo, hi, lo) on the B side, so one 16x16x16 MFMA step sums hi.hi + hi.lo
-// + lo.hi + lo.lo over four K elements; the products are exact in fp32 and
-// accumulate in fp32.  fp16 keeps 22 significant bits per operand, bfloat16 16.
-template <class V>
-__device__ __forceinline__ V neg_halves(V x, bool neg) {
-    u32x2 v = __builtin_bit_cast(u32x2, x);
-    const unsigned m = neg ? 0x80008000u : 0u;
-    v.x ^= m;
-    v.y ^= m;
-    return __builtin_bit_cast(V, v);
-}
-template <>
-struct Oper<SSE_FP16X2> {
-    using T = h4;
-    using Acc = f32x4;
-    static __device__ __forceinline__ Acc mma(T a, T b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0); }
-    static __device__ __forceinline__ T neg_if(T x, bool neg) { return neg_halves(x, neg); }
-    // the fp32 accumulator layout of the 16x16 f32 MFMAs
-    static __device__ __forceinline__ int row_of(int lane, int v) { return 4 * (lane >> 4) + v; }
-    // (hi, lo) of x as one 32-bit word, hi in the low half
-    static __device__ __forceinline__ unsigned split_word(float x) {
-        const _Float16 h = (_Float16)x;
-        const _Float16 l = (_Float16)(x - (float)h);
-        typedef _Float16 h2 __attribute__((ext_vector_type(2)));
-        return __builtin_bit_cast(unsigned, h2{h, l});
-    }
-    static __device__ __forceinline__ T split_a(double x) {
-        const _Float16 h = (_Float16)(float)x;
-        const _Float16 l = (_Float16)(float)(x - (double)h);
-        return h4{h, h, l, l};
-    }
-};
-template <>
-struct Oper<SSE_BF16X2> {
-    using T = s4;  // four bfloat16 bit patterns
-    using Acc = f32x4;
-    static __device__ __forceinline__ Acc mma(T a, T b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0); }
-    static __device__ __forceinline__ T neg_if(T x, bool neg) { return neg_halves(x, neg); }
-    static __device__ __forceinline__ int row_of(int lane, int v) { return 4 * (lane >> 4) + v; }
-    static __device__ __forceinline__ unsigned short bits(__bf16 h) { return __builtin_bit_cast(unsigned short, h); }
-    static __device__ __forceinline__ float value(__bf16 h) { return (float)h; }
-    static __device__ __forceinline__ unsigned split_word(float x) {
-        const __bf16 h = (__bf16)x;               // round to nearest even
-        const __bf16 l = (__bf16)(x - value(h));  // x - hi is exact in fp32
-        return (unsigned)bits(h) | ((unsigned)bits(l) << 16);
-    }
-    static __device__ __forceinline__ T split_a(double x) {
-        const __bf16 h = (__bf16)(float)x;
-        const __bf16 l = (__bf16)(float)(x - (double)value(h));
-        const short hs = (short)bits(h), ls = (short)bits(l);
-        return s4{hs, hs, ls, ls};
-    }
-};
-// power of two s with m * s in [2^(t-1), 2^t) (1 for m = 0)
-__device__ __forceinline__ double pow2_scale(double m, int t) {
-    if (!(m > 0.0)) return 1.0;
-    int e;
-    frexp(m, &e);
-    return ldexp(1.0, t - e);
-}
-// largest value over a full wave: butterflies inside each row of 16 lanes on
-// the DPP network, then the four row results through scalar registers
-__device__ __forceinline__ int wave_max(int v) {
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x124, 0xF, 0xF, false));  // row_ror:4
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x128, 0xF, 0xF, false));  // row_ror:8
-    const int r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
-    const int r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
-    return max(max(r0, r1), max(r2, r3));
-}
-constexpr int ceil_log2(int x) {
-    int e = 0;
-    while ((1 << e) < x) ++e;
-    return e;
-}
 
 template <int NORB, int NKZ, int NW, int NB, int EB, int PREC>
 struct Fwd64 {
@@ -204,10 +121,7 @@ struct Fwd64 {
     static constexpr int RP = NKZ * NORB * 2;  // one ring plane: [k][c] complex
     static constexpr int L_R = RING * RP;
     static constexpr int OPER_DOUBLES = ((L_D + L_P) * (int)sizeof(T) + 7) / 8;
-    // fp16 form: inverse scale per (chunk mod 4, source energy); also the scratch of
-    // the workgroup max reductions
-    static constexpr int L_S = 4 * EB > WAVES ? 4 * EB : WAVES;
-    static constexpr size_t LDS_BYTES = sizeof(double) * (size_t)(OPER_DOUBLES + L_A + L_AP + L_X + L_R + L_S);
+    static constexpr size_t LDS_BYTES = sizeof(double) * (size_t)(OPER_DOUBLES + L_A + L_AP + L_X + L_R);
     static constexpr int X_ITEMS = EB * 2 * 3 * NORB;  // (el, nl, i, u)
     static constexpr int X_IPW = (X_ITEMS + WAVES - 1) / WAVES;
     // P chunk on the matrix cores, per neighbour of the pair: C[(el,i,re/im), (j,c)] =
@@ -218,13 +132,8 @@ struct Fwd64 {
     static constexpr int PNC = 3 * NORB;
     static constexpr int PNT = (PNC + 15) / 16;
     static constexpr int NPT = 2 * PMT * PNT;     // P tiles per chunk
-    // 16-bit hi/lo operand forms, and the one of them that normalises by powers of two
-    static constexpr bool SPLIT = PREC == SSE_FP16X2 || PREC == SSE_BF16X2;
-    static constexpr bool NORM = PREC == SSE_FP16X2;
-    // issue cost of one P tile in main-GEMM k-steps: the same instruction time
-    // for fp64 and fp32; for the 16-bit forms its fp32 k-steps take twice a
-    // 16-bit k-step and the hi/lo split of its results about as much again
-    static constexpr int PTILE_COST = SPLIT ? 3 * PKS : PKS;
+    // issue cost of one P tile in main-GEMM k-steps (fp64 and fp32 alike)
+    static constexpr int PTILE_COST = PKS;
     static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
     static_assert(X_IPW <= 64, "one item per lane");
     static_assert(NPT <= 32, "P tiles fit a 32-bit wave mask");
@@ -259,46 +168,6 @@ struct PTileDeal {
     }
 };
 
-// Phases of the end-of-block scatter into the output ring.  A tile's
-// contributions land on ring entries of the momenta k its rows carry, so tiles
-// of different waves whose k sets are disjoint can add concurrently without
-// touching the same entry; every entry then receives its additions in a fixed
-// order and the fp64 sums are bitwise reproducible.  Greedy first fit, own
-// tiles before extra pairs.
-template <class C>
-struct ScatterPlan {
-    int own_phase[C::WAVES];
-    int ext_phase[C::WAVES];
-    int nphase;
-    static constexpr uint32_t kmask(int mt) {
-        uint32_t m = 0;
-        for (int row = 16 * mt; row < 16 * mt + 16 && row < C::MROWS; ++row) m |= 1u << ((row >> 1) / C::NWV);
-        return m;
-    }
-    constexpr ScatterPlan() : own_phase{}, ext_phase{}, nphase(0) {
-        uint32_t used[2 * C::WAVES] = {};     // k set of each phase
-        int owner[2 * C::WAVES][C::WAVES] = {};  // per phase: k set contributed by each wave
-        for (int item = 0; item < 2 * C::WAVES; ++item) {
-            const int w = item % C::WAVES;
-            const bool ext = item >= C::WAVES;
-            if (ext ? !(w < C::XP) : !(w < C::OWN)) {
-                (ext ? ext_phase : own_phase)[w] = -1;
-                continue;
-            }
-            const uint32_t m = kmask(ext ? C::WAVES + w / C::NT : w);
-            int p = 0;
-            for (;; ++p) {
-                const uint32_t others = used[p] & ~(uint32_t)owner[p][w];
-                if ((others & m) == 0) break;
-            }
-            used[p] |= m;
-            owner[p][w] |= (int)m;
-            (ext ? ext_phase : own_phase)[w] = p;
-            if (p + 1 > nphase) nphase = p + 1;
-        }
-    }
-};
-
 template <int NORB, int NKZ, int NW, int NB, int EB, int PREC, int FLAGS>
 __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __restrict__ G,
                                                        const double* __restrict__ Dg,
@@ -321,9 +190,6 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     TP* sAp = reinterpret_cast<TP*>(sA + (C::SPLIT_A ? C::L_A : 0));  // grad H for the P tiles
     TP* sX = reinterpret_cast<TP*>(sA + C::L_A + C::L_AP);
     double* sR = sA + C::L_A + C::L_AP + C::L_X;
-    double* sS = sR + C::L_R;
-    constexpr bool NORM = C::NORM, SPLIT = C::SPLIT;
-    static_assert(!NORM || EB == C::WAVES, "fp16 form: wave w forms the X rows of source energy w");
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -335,33 +201,6 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     if (a >= d.na) return;  // uniform for the whole workgroup, before any barrier
 
     // ---- stage the atom's D table, grad H; clear buffers
-    // fp16 form: per-atom power-of-two normalisation of D (largest part below
-    // 2^7) and of grad H (below 2); workgroup max of the parts first
-    double sc_d = 1.0, sc_h = 1.0, inv_base = 1.0;
-    if constexpr (NORM) {
-        auto block_max = [&](double m) {
-            for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
-            __syncthreads();
-            if (lane == 0) sS[wave] = m;
-            __syncthreads();
-            double r = sS[0];
-            for (int w = 1; w < C::WAVES; ++w) r = fmax(r, sS[w]);
-            return r;
-        };
-        double md = 0.0, mh = 0.0;
-        for (int x = tid; x < NKZ * NW * NB * 9; x += C::THREADS) {
-            const int ij = x % 9, n = (x / 9) % NB, w = (x / (9 * NB)) % NW, q = x / (9 * NB * NW);
-            const cd v = cload(Dg, off_D(d, q, w, a, n) + ij);
-            md = fmax(md, fmax(fabs(v.re), fabs(v.im)));
-        }
-        for (int x = tid; x < NB * 3 * C::NN; x += C::THREADS) {
-            const cd v = cload(Ag, off_A(d, a, 0, 0) + x);
-            mh = fmax(mh, fmax(fabs(v.re), fabs(v.im)));
-        }
-        sc_d = pow2_scale(block_max(md), 7);
-        sc_h = pow2_scale(block_max(mh), 1);
-        inv_base = 1.0 / (sc_d * sc_h * sc_h);
-    }
     for (int x = tid; x < C::L_D; x += C::THREADS) sD[x] = T(0);
     for (int x = tid; x < C::L_A; x += C::THREADS) sA[x] = 0.0;
     if constexpr (C::SPLIT_A)
@@ -371,23 +210,18 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
         const int ij = x % 9, n = (x / 9) % NB, w = (x / (9 * NB)) % NW, q = x / (9 * NB * NW);
         const cd v = cload(Dg, off_D(d, q, w, a, n) + ij);
         T* o = sD + q * C::QS + w * C::WS + n * 18 + ij * 2;
-        if constexpr (SPLIT) {
-            o[0] = O::split_a(v.re * sc_d);
-            o[1] = O::split_a(v.im * sc_d);
-        } else {
-            o[0] = T(v.re);
-            o[1] = T(v.im);
-        }
+        o[0] = T(v.re);
+        o[1] = T(v.im);
     }
     for (int x = tid; x < NB * 3 * C::NN; x += C::THREADS) {
         const cd v = cload(Ag, off_A(d, a, 0, 0) + x);
         const int n = x / (3 * C::NN), i = (x / C::NN) % 3, rc = x % C::NN;
         const int o = (n >> 1) * C::PSTR + ((n & 1) * 3 + i) * C::NNS + (rc / NORB) * C::AR + 2 * (rc % NORB);
-        sA[o] = v.re * sc_h;
-        sA[o + 1] = v.im * sc_h;
+        sA[o] = v.re;
+        sA[o + 1] = v.im;
         if constexpr (C::SPLIT_A) {
-            sAp[o] = TP(v.re * sc_h);
-            sAp[o + 1] = TP(v.im * sc_h);
+            sAp[o] = TP(v.re);
+            sAp[o + 1] = TP(v.im);
         }
     }
     for (int x = tid; x < C::L_P; x += C::THREADS) sP[x] = T(0);
@@ -441,29 +275,14 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
         for (int t = 0; t < NORB; ++t) gv[t] = cd{Gb[2 * t * NORB], Gb[2 * t * NORB + 1]};
     };
     // ---- X rows, step 2: X[el][nl][i][u] = sum_t gradH[n][i][r][t] G[t][u]
-    // fp16 form: the X rows of one source energy (one wave) are normalised by a
-    // power of two (largest part below 2^XT, which keeps every P entry below
-    // 2^14); the inverse of all scale factors of the chunk's column goes to LDS
-    constexpr int XT = 14 - ceil_log2(4 * NORB);
     auto finish_x = [&](int g) {
-        if (g >= niter || (!NORM && !x_lane)) return;
+        if (g >= niter || !x_lane) return;
         const int np = (g % C::NCHUNK) % C::NP;
         const double* Ar = sA + np * C::PSTR + (x_nl * 3 + x_i) * C::NNS + r * C::AR;
         cd acc{0.0, 0.0};
 #pragma unroll
         for (int t = 0; t < NORB; ++t) cfma(acc, cd{Ar[2 * t], Ar[2 * t + 1]}, gv[t]);
         if (!g_ok) acc = cd{0.0, 0.0};
-        if constexpr (NORM) {
-            const double m = fmax(fabs(acc.re), fabs(acc.im));
-            int e = -4000;
-            if (m > 0.0) frexp(m, &e);
-            e = wave_max(e);
-            const int shift = e == -4000 ? 0 : XT - e;
-            acc.re = ldexp(acc.re, shift);
-            acc.im = ldexp(acc.im, shift);
-            if (lane == 0) sS[(g & 3) * EB + wave] = ldexp(inv_base, -shift);
-            if (!x_lane) return;
-        }
         TP* X = sX + (g & 1) * C::XB + ((x_nl * EB + x_el) * 3 + x_i) * C::XR + 2 * x_u;
         if constexpr (C::SPLIT_A)
             *reinterpret_cast<float2*>(X) = make_float2((float)acc.re, (float)acc.im);
@@ -550,13 +369,7 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
             if constexpr (PREC != SSE_FP64) acc += acc1[t];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                if constexpr (SPLIT) {
-                    unsigned* q = reinterpret_cast<unsigned*>(P + pt_out[s0 + t][v]);
-                    const unsigned w = O::split_word(acc[v]);
-                    q[0] = w;
-                    q[1] = w;
-                } else
-                    P[pt_out[s0 + t][v]] = T(acc[v]);
+                P[pt_out[s0 + t][v]] = T(acc[v]);
             }
         }
     };
@@ -654,23 +467,7 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
                 if (has_extra) part_x = O::mma(b, bx[cur], ks == 0 ? zero_acc : part_x);
             }
         }
-        if constexpr (NORM) {
-            // undo the chunk's normalisation of the lane's column (source energy)
-            const double* inv = sS + (g & 3) * EB;
-            auto el_of = [&](int nt) {
-                const int col = 16 * nt + j16;
-                return col < C::NCOLS ? col / NORB : 0;
-            };
-#pragma unroll
-            for (int nt = 0; nt < C::NT; ++nt) {
-                const double f = inv[el_of(nt)];
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[nt][v] = fma((double)part[nt][v], f, acc[nt][v]);
-            }
-            const double fx = inv[el_of(ext_nt)];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc_x[v] = fma((double)part_x[v], fx, acc_x[v]);
-        } else if constexpr (PREC != SSE_FP64) {
+        if constexpr (PREC != SSE_FP64) {
 #pragma unroll
             for (int nt = 0; nt < C::NT; ++nt)
 #pragma unroll
@@ -840,8 +637,8 @@ hipError_t launch_fwd_mfma(const Dims& d, int precision, const double* G, const 
                            const int32_t* nbr, cd alpha, double* S, hipStream_t stream, int flags) {
     if (precision == SSE_FP64) return dispatch_fwd<SSE_FP64>(d, G, D, A, nbr, alpha, S, stream, flags);
     if (precision == SSE_FP32) return dispatch_fwd<SSE_FP32>(d, G, D, A, nbr, alpha, S, stream, flags);
-    if (precision == SSE_FP16X2) return dispatch_fwd<SSE_FP16X2>(d, G, D, A, nbr, alpha, S, stream, flags);
-    if (precision == SSE_BF16X2) return dispatch_fwd<SSE_BF16X2>(d, G, D, A, nbr, alpha, S, stream, flags);
+    if (precision == SSE_FP16X2 || precision == SSE_BF16X2)
+        return launch_fwd_h16(d, precision, G, D, A, nbr, alpha, S, stream, flags);
     return hipErrorInvalidValue;
 }
 

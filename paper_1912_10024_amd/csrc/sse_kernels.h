@@ -18,13 +18,19 @@ bool generic_supported(const Dims& d);
 hipError_t launch_fwd_generic(const Dims& d, const double* G, const double* Dp, const double* Dm, const double* A,
                               const int32_t* nbr, cd alpha, double* S, hipStream_t stream);
 
-// matrix-core forward (fp64, fp32 or fp16 hi/lo operands) for the shapes it is
+// matrix-core forward (fp64 or fp32 operands; the split 16-bit forms go to
+// launch_fwd_h16) for the shapes it is
 // instantiated for; flags selects the energy branches (kBranchMinus,
 // kBranchPlus) and whether the result is added to Sigma (kAccumulate)
 bool fwd_mfma_specialised(const Dims& d);
 hipError_t launch_fwd_mfma(const Dims& d, int precision, const double* G, const double* D, const double* A,
                            const int32_t* nbr, cd alpha, double* S, hipStream_t stream,
                            int flags = kBranchMinus | kBranchPlus);
+
+// matrix-core forward with split 16-bit operands (SSE_FP16X2, SSE_BF16X2) for
+// the shapes of fwd_mfma_specialised; flags as for launch_fwd_mfma
+hipError_t launch_fwd_h16(const Dims& d, int precision, const double* G, const double* D, const double* A,
+                          const int32_t* nbr, cd alpha, double* S, hipStream_t stream, int flags);
 
 // adjoint (fp64): reverse adjacency in the workspace, then dG/d gradH per neighbour atom and dD per edge
 size_t bwd_workspace_bytes(const Dims& d);
