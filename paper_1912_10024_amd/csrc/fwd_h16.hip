@@ -143,9 +143,9 @@ struct H16Cfg {
     // P chunk (16-byte units) [row 4 t + kk][column (E', c)]: (hi | lo << 16) of four
     // entries, two buffers; the unit after each buffer takes the padding results
     // of the P tiles
-    static constexpr int NCP = NT * 16;
+    static constexpr int NCP = NT * 16 + 1;  // odd: the rows of a unit's Re and Im hit different banks
     static constexpr int TRASH = 4 * NG * NCP;
-    static constexpr int PBS = TRASH + 1;
+    static constexpr int PBS = TRASH + EB * NORB;  // spare units: four stores at a stride of 4 Norb words
     static constexpr int L_P = 2 * PBS;
     // P tiles, one GEMM per neighbour: rows (E', i), K pairs u (Re, Im), columns (j, c, re/im)
     static constexpr int PM = EB * 3;
@@ -156,7 +156,8 @@ struct H16Cfg {
     static constexpr int HCOLS = PNT * 16;
     static constexpr int HZ = NB * NORB * HCOLS;   // a zero pair
     static constexpr int L_H = HZ + 2;             // conj(grad H) embedding [n][u][col], P form
-    static constexpr int XB = NB * NORB * PM;      // one buffer of X rows [n][u][i EB + E'], M form
+    static constexpr int XRS = PM + 1;             // odd stride of the (n, u) row blocks (bank spread)
+    static constexpr int XB = NB * NORB * XRS;     // one buffer of X rows [n][u][i EB + E'], M form
     static constexpr int XZ = 2 * XB;              // a zero pair read by padding rows and pairs
     static constexpr int L_X = 2 * XB + 2;
     static constexpr int UNITS = NB * PNT;         // P-tile units (neighbour, column tile)
@@ -330,7 +331,7 @@ __global__ __launch_bounds__(512) void fwd_h16_kernel(Dims d, const double* __re
             if (lane == 0) sS[(g & 3) * EB + wave] = ldexp(inv_base, -shift);
         }
         if (!x_lane) return;
-        uint2* X = sX + (g & 1) * C::XB + (x_n * NORB + x_u) * C::PM + wave;
+        uint2* X = sX + (g & 1) * C::XB + (x_n * NORB + x_u) * C::XRS + wave;
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             double re = x[i].re, im = x[i].im;
@@ -366,7 +367,7 @@ __global__ __launch_bounds__(512) void fwd_h16_kernel(Dims d, const double* __re
 #pragma unroll
                 for (int mt = 0; mt < C::PMT; ++mt) {
                     const int row = 16 * mt + j16;
-                    const uint2* xp = (u_ok && row < C::PM) ? Xb + (n * NORB + u) * C::PM + row : sX + C::XZ;
+                    const uint2* xp = (u_ok && row < C::PM) ? Xb + (n * NORB + u) * C::XRS + row : sX + C::XZ;
                     acc[mt] = O::mma(m_operand(*xp), hb, acc[mt]);
                 }
             }
@@ -383,9 +384,8 @@ __global__ __launch_bounds__(512) void fwd_h16_kernel(Dims d, const double* __re
                 const int prow = 4 * (e >> 3) + 2 * ((e >> 2) & 1) + comp;
                 const bool ok = i < 3 && col < C::PN;
                 uint32_t* dst = P + (ok ? (prow * C::NCP + 4 * (kk & 1) * NORB + c) * 4 + (e & 3) : 4 * C::TRASH);
-                const int step = ok ? 4 * NORB : 0;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) dst[v * step] = O::split(acc[mt][v]);
+                for (int v = 0; v < 4; ++v) dst[v * 4 * NORB] = O::split(acc[mt][v]);
             }
         }
     };
