@@ -45,3 +45,15 @@ def sse_forward(G, D, dH, nbr, alpha=1j) -> torch.Tensor:
     Gg = gather_shifted(G, nbr, nqz, nw)
     out = torch.einsum("qmanij,anirt,keaqmsntu,anjcu->kearc", D, dH, Gg, dH.conj())
     return alpha * out
+
+
+def sse_forward_ex(G, Dp, Dm, dH, dHba, nbr, alpha=1j) -> torch.Tensor:
+    """Eq. 3 over signed frequencies (Dp for the terms with G at E - w, Dm for
+    those at E + w) with the stored right factor dHba[a, n, j] = grad_j H_ba
+    (None: dH[a, n, j]^H), as one einsum over the gathered tensor."""
+    nqz, nw = Dp.shape[0], Dp.shape[1]
+    Gg = gather_shifted(G, nbr, nqz, nw)
+    Ds = torch.stack([Dp, Dm], dim=2)                                  # [q, m, s, a, n, i, j]
+    right = dHba if dHba is not None else dH.conj().transpose(-1, -2)  # [a, n, j, u, c]
+    out = torch.einsum("qmsanij,anirt,keaqmsntu,anjuc->kearc", Ds, dH, Gg, right)
+    return alpha * out

@@ -62,9 +62,13 @@ def _open(path):
     lib.oracle_pse_forward.argtypes = [P, P, P, P, P, ctypes.c_double, ctypes.c_double, P]
     lib.oracle_sse_points_signed.argtypes = [P, P, P, P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_int64, P, P]
     lib.oracle_sse_forward_signed.argtypes = [P, P, P, P, P, P, ctypes.c_double, ctypes.c_double, P]
+    lib.oracle_sse_points_ex.argtypes = [P, P, P, P, P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_int64, P, P]
+    lib.oracle_sse_forward_ex.argtypes = [P, P, P, P, P, P, P, ctypes.c_double, ctypes.c_double, P]
+    lib.oracle_sse_backward_signed.argtypes = [P, P, P, P, P, P, ctypes.c_double, ctypes.c_double, P, P, P, P, P]
     for f in (lib.oracle_sse_points, lib.oracle_sse_forward, lib.oracle_sse_backward, lib.oracle_num_threads,
               lib.oracle_combine_d, lib.oracle_pse_points, lib.oracle_pse_forward, lib.oracle_sse_points_signed,
-              lib.oracle_sse_forward_signed):
+              lib.oracle_sse_forward_signed, lib.oracle_sse_points_ex, lib.oracle_sse_forward_ex,
+              lib.oracle_sse_backward_signed):
         f.restype = ctypes.c_int
     return lib
 
@@ -163,6 +167,58 @@ def sse_points_signed(dims, G, Dp, Dm, dH, nbr, pts, alpha=1j, lib=None) -> np.n
     return out
 
 
+def sse_forward_ex(dims, G, Dp, Dm, dH, dHba, nbr, alpha=1j, lib=None) -> np.ndarray:
+    """Full Sigma of Eq. 3 with one coefficient table per sign of the frequency
+    and the stored right factor dHba[a, n, j] = grad_j H_ba (None: dH[a, n, j]^H)."""
+    _check_inputs(dims, G, Dp, dH, nbr)
+    _check(Dm, dims.d_shape, np.complex128, "Dm")
+    if dHba is not None:
+        _check(dHba, dims.dh_shape, np.complex128, "dHba")
+    out = np.zeros(dims.sigma_shape, dtype=np.complex128)
+    dd = _dims_array(dims)
+    rc = (lib or _load()).oracle_sse_forward_ex(_ptr(dd), _ptr(G), _ptr(Dp), _ptr(Dm), _ptr(dH), _ptr(dHba),
+                                                _ptr(nbr), float(np.real(alpha)), float(np.imag(alpha)), _ptr(out))
+    if rc:
+        raise RuntimeError(f"oracle_sse_forward_ex failed with status {rc}")
+    return out
+
+
+def sse_points_ex(dims, G, Dp, Dm, dH, dHba, nbr, pts, alpha=1j, lib=None) -> np.ndarray:
+    """Blocks of sse_forward_ex at output points pts[p] = (k, e, a)."""
+    _check_inputs(dims, G, Dp, dH, nbr)
+    _check(Dm, dims.d_shape, np.complex128, "Dm")
+    if dHba is not None:
+        _check(dHba, dims.dh_shape, np.complex128, "dHba")
+    pts = np.ascontiguousarray(np.asarray(pts, dtype=np.int64).reshape(-1, 3))
+    out = np.zeros((pts.shape[0], dims.norb, dims.norb), dtype=np.complex128)
+    dd = _dims_array(dims)
+    rc = (lib or _load()).oracle_sse_points_ex(_ptr(dd), _ptr(G), _ptr(Dp), _ptr(Dm), _ptr(dH), _ptr(dHba),
+                                               _ptr(nbr), float(np.real(alpha)), float(np.imag(alpha)),
+                                               pts.shape[0], _ptr(pts), _ptr(out))
+    if rc:
+        raise RuntimeError(f"oracle_sse_points_ex failed with status {rc}")
+    return out
+
+
+def sse_backward_signed(dims, G, Dp, Dm, dH, nbr, dSigma, alpha=1j, need=("G", "D", "dH"), lib=None):
+    """Gradients (dG, dDp, dDm, ddH) of a real scalar through sse_forward_signed,
+    with dL/dSigma = dSigma (PyTorch convention)."""
+    _check_inputs(dims, G, Dp, dH, nbr)
+    _check(Dm, dims.d_shape, np.complex128, "Dm")
+    _check(dSigma, dims.sigma_shape, np.complex128, "dSigma")
+    dG = np.zeros(dims.g_shape, dtype=np.complex128) if "G" in need else None
+    dDp = np.zeros(dims.d_shape, dtype=np.complex128) if "D" in need else None
+    dDm = np.zeros(dims.d_shape, dtype=np.complex128) if "D" in need else None
+    ddH = np.zeros(dims.dh_shape, dtype=np.complex128) if "dH" in need else None
+    dd = _dims_array(dims)
+    rc = (lib or _load()).oracle_sse_backward_signed(_ptr(dd), _ptr(G), _ptr(Dp), _ptr(Dm), _ptr(dH), _ptr(nbr),
+                                                     float(np.real(alpha)), float(np.imag(alpha)), _ptr(dSigma),
+                                                     _ptr(dG), _ptr(dDp), _ptr(dDm), _ptr(ddH))
+    if rc:
+        raise RuntimeError(f"oracle_sse_backward_signed failed with status {rc}")
+    return dG, dDp, dDm, ddH
+
+
 def sse_backward(dims, G, D, dH, nbr, dSigma, alpha=1j, need=("G", "D", "dH"), lib=None):
     """Gradients (dG, dD, ddH) of a real scalar with dL/dSigma = dSigma (PyTorch convention)."""
     _check_inputs(dims, G, D, dH, nbr)
@@ -256,6 +312,15 @@ class Bound:
 
     def sse_backward(self, *a, **k):
         return sse_backward(*a, lib=self.lib, **k)
+
+    def sse_forward_ex(self, *a, **k):
+        return sse_forward_ex(*a, lib=self.lib, **k)
+
+    def sse_points_ex(self, *a, **k):
+        return sse_points_ex(*a, lib=self.lib, **k)
+
+    def sse_backward_signed(self, *a, **k):
+        return sse_backward_signed(*a, lib=self.lib, **k)
 
     def sse_status(self, *a, **k):
         return sse_status(*a, lib=self.lib, **k)

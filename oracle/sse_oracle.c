@@ -19,7 +19,9 @@
  * integral of Eq. 3 over signed frequencies on a grid of Nw positive ones.
  *
  * A[a,n,i] is grad_i H for the pair (a, b = nbr[a,n]); grad_j H_ba = A[a,n,j]^H
- * because H is Hermitian.  Every product is an Norb x Norb complex matrix
+ * because H is Hermitian.  The *_ex functions also take the stored blocks
+ * Aba[a,n,j] = grad_j H_ba (layout of A) as the right factor of Eq. 3 in place
+ * of A[a,n,j]^H; a NULL Aba means the Hermitian reading.  Every product is an Norb x Norb complex matrix
  * product; D[...,i,j] is a complex scalar; only the diagonal block of Sigma is
  * formed (the paper keeps only the diagonal blocks of the electron SSE).
  *
@@ -112,13 +114,24 @@ static void acc_mul_adj(int64_t N, cplx d, const cplx* T, const double* Y, cplx*
         }
 }
 
+/* acc[r][c] += d * (T . Y)[r][c] */
+static void acc_mul(int64_t N, cplx d, const cplx* T, const double* Y, cplx* acc) {
+    for (int64_t r = 0; r < N; ++r)
+        for (int64_t c = 0; c < N; ++c) {
+            cplx s = { 0.0, 0.0 };
+            for (int64_t u = 0; u < N; ++u) s = c_add(s, c_mul(T[r * N + u], c_at(Y, u * N + c)));
+            acc[r * N + c] = c_add(acc[r * N + c], c_mul(d, s));
+        }
+}
+
 /* One output block Sigma[k,e,a] (Eq. 3), written to out as N*N complex.
  * Eq. 3 integrates over signed frequencies; with the Nw stored frequencies
  * w_m > 0 the s = +1 terms (G at e - m) carry the coefficient at +w_m (Dp) and
  * the s = -1 terms (G at e + m) the coefficient at -w_m (Dm).  The one-table
- * form reads the same table for both (Dm == Dp). */
+ * form reads the same table for both (Dm == Dp).  The right factor is
+ * grad_j H_ba: Aba[a,n,j] when given, else A[a,n,j]^H. */
 static void sigma_block(const odims* d, const double* G, const double* Dp, const double* Dm, const double* A,
-                        const int32_t* nbr, cplx alpha, int64_t k, int64_t e, int64_t a,
+                        const double* Aba, const int32_t* nbr, cplx alpha, int64_t k, int64_t e, int64_t a,
                         cplx* acc, cplx* T, double* out) {
     const int64_t N = d->norb;
     for (int64_t x = 0; x < N * N; ++x) { acc[x].re = 0.0; acc[x].im = 0.0; }
@@ -136,7 +149,10 @@ static void sigma_block(const odims* d, const double* G, const double* Dp, const
                         mat_mul(N, A + 2 * off_A(d, a, n, i), Gb, T);
                         for (int j = 0; j < 3; ++j) {
                             const cplx dij = c_at(D, off_D(d, q, m - 1, a, n, i, j));
-                            acc_mul_adj(N, dij, T, A + 2 * off_A(d, a, n, j), acc);
+                            if (Aba)
+                                acc_mul(N, dij, T, Aba + 2 * off_A(d, a, n, j), acc);
+                            else
+                                acc_mul_adj(N, dij, T, A + 2 * off_A(d, a, n, j), acc);
                         }
                     }
                 }
@@ -159,10 +175,11 @@ int oracle_num_threads(void) {
 }
 
 /* Sigma at a list of output points pts[p] = (k, e, a); out is [npts][norb][norb].
- * Dp: coefficients at +w (terms with G at e - m), Dm: at -w (G at e + m). */
-int oracle_sse_points_signed(const int64_t* dims, const double* G, const double* Dp, const double* Dm,
-                             const double* A, const int32_t* nbr, double alpha_re, double alpha_im,
-                             int64_t npts, const int64_t* pts, double* out) {
+ * Dp: coefficients at +w (terms with G at e - m), Dm: at -w (G at e + m);
+ * Aba: stored grad_j H_ba blocks, or NULL for A^H. */
+int oracle_sse_points_ex(const int64_t* dims, const double* G, const double* Dp, const double* Dm,
+                         const double* A, const double* Aba, const int32_t* nbr, double alpha_re, double alpha_im,
+                         int64_t npts, const int64_t* pts, double* out) {
     odims d;
     int rc = read_dims(dims, &d);
     if (rc) return rc;
@@ -185,7 +202,7 @@ int oracle_sse_points_signed(const int64_t* dims, const double* G, const double*
         } else {
 #pragma omp for schedule(dynamic, 1)
             for (int64_t p = 0; p < npts; ++p)
-                sigma_block(&d, G, Dp, Dm, A, nbr, alpha, pts[3 * p], pts[3 * p + 1], pts[3 * p + 2], acc, T,
+                sigma_block(&d, G, Dp, Dm, A, Aba, nbr, alpha, pts[3 * p], pts[3 * p + 1], pts[3 * p + 2], acc, T,
                             out + 2 * NN * p);
         }
         free(acc);
@@ -194,17 +211,24 @@ int oracle_sse_points_signed(const int64_t* dims, const double* G, const double*
     return fail ? 7 : 0;
 }
 
+/* One table per sign of the frequency, Hermitian reading of grad_j H_ba. */
+int oracle_sse_points_signed(const int64_t* dims, const double* G, const double* Dp, const double* Dm,
+                             const double* A, const int32_t* nbr, double alpha_re, double alpha_im,
+                             int64_t npts, const int64_t* pts, double* out) {
+    return oracle_sse_points_ex(dims, G, Dp, Dm, A, NULL, nbr, alpha_re, alpha_im, npts, pts, out);
+}
+
 /* The one-table form: the same coefficient table for both signs of the frequency. */
 int oracle_sse_points(const int64_t* dims, const double* G, const double* D, const double* A,
                       const int32_t* nbr, double alpha_re, double alpha_im, int64_t npts,
                       const int64_t* pts, double* out) {
-    return oracle_sse_points_signed(dims, G, D, D, A, nbr, alpha_re, alpha_im, npts, pts, out);
+    return oracle_sse_points_ex(dims, G, D, D, A, NULL, nbr, alpha_re, alpha_im, npts, pts, out);
 }
 
-/* Full Sigma [nkz][ne][na][norb][norb]; Dp and Dm as for oracle_sse_points_signed. */
-int oracle_sse_forward_signed(const int64_t* dims, const double* G, const double* Dp, const double* Dm,
-                              const double* A, const int32_t* nbr, double alpha_re, double alpha_im,
-                              double* Sigma) {
+/* Full Sigma [nkz][ne][na][norb][norb]; Dp, Dm and Aba as for oracle_sse_points_ex. */
+int oracle_sse_forward_ex(const int64_t* dims, const double* G, const double* Dp, const double* Dm,
+                          const double* A, const double* Aba, const int32_t* nbr, double alpha_re,
+                          double alpha_im, double* Sigma) {
     odims d;
     int rc = read_dims(dims, &d);
     if (rc) return rc;
@@ -225,7 +249,7 @@ int oracle_sse_forward_signed(const int64_t* dims, const double* G, const double
 #pragma omp for schedule(dynamic, 4)
             for (int64_t x = 0; x < nblk; ++x) {
                 const int64_t a = x % d.na, e = (x / d.na) % d.ne, k = x / (d.na * d.ne);
-                sigma_block(&d, G, Dp, Dm, A, nbr, alpha, k, e, a, acc, T, Sigma + 2 * off_S(&d, k, e, a));
+                sigma_block(&d, G, Dp, Dm, A, Aba, nbr, alpha, k, e, a, acc, T, Sigma + 2 * off_S(&d, k, e, a));
             }
         }
         free(acc);
@@ -234,10 +258,17 @@ int oracle_sse_forward_signed(const int64_t* dims, const double* G, const double
     return fail ? 7 : 0;
 }
 
+/* Full Sigma over signed frequencies, Hermitian reading of grad_j H_ba. */
+int oracle_sse_forward_signed(const int64_t* dims, const double* G, const double* Dp, const double* Dm,
+                              const double* A, const int32_t* nbr, double alpha_re, double alpha_im,
+                              double* Sigma) {
+    return oracle_sse_forward_ex(dims, G, Dp, Dm, A, NULL, nbr, alpha_re, alpha_im, Sigma);
+}
+
 /* Full Sigma, one-table form (the same table for both signs of the frequency). */
 int oracle_sse_forward(const int64_t* dims, const double* G, const double* D, const double* A,
                        const int32_t* nbr, double alpha_re, double alpha_im, double* Sigma) {
-    return oracle_sse_forward_signed(dims, G, D, D, A, nbr, alpha_re, alpha_im, Sigma);
+    return oracle_sse_forward_ex(dims, G, D, D, A, NULL, nbr, alpha_re, alpha_im, Sigma);
 }
 
 /*
@@ -251,10 +282,13 @@ int oracle_sse_forward(const int64_t* dims, const double* G, const double* D, co
  *   dA[a,n,j]            += alpha d g^H A_i B
  * (derived from dL = Re <g, dSigma>).  dG slots >= 1 are not read by the
  * forward map and are set to zero.  Any of dG, dD, dA may be NULL.
+ * Over signed frequencies the s = +1 terms read Dp and feed dDp, the s = -1
+ * terms read Dm and feed dDm (the one-table form passes the same table and the
+ * same gradient array for both).
  */
-static void adjoint_terms_for_atom(const odims* d, const double* G, const double* D, const double* A,
-                                   const int32_t* nbr, cplx alpha, const double* gS, int64_t a,
-                                   double* dD, double* dA, cplx* work) {
+static void adjoint_terms_for_atom(const odims* d, const double* G, const double* Dp, const double* Dm,
+                                   const double* A, const int32_t* nbr, cplx alpha, const double* gS, int64_t a,
+                                   double* dDp, double* dDm, double* dA, cplx* work) {
     const int64_t N = d->norb, NN = N * N;
     cplx* P = work;          /* A_i B A_j^H */
     cplx* X = work + NN;     /* A_i B       */
@@ -270,6 +304,8 @@ static void adjoint_terms_for_atom(const odims* d, const double* G, const double
                     for (int s = +1; s >= -1; s -= 2) {
                         const int64_t ep = e - s * m;
                         if (ep < 0 || ep >= d->ne) continue;
+                        const double* D = s > 0 ? Dp : Dm;
+                        double* dD = s > 0 ? dDp : dDm;
                         for (int64_t n = 0; n < d->nb; ++n) {
                             const int64_t b = nbr[a * d->nb + n];
                             const double* B = G + 2 * off_G(d, kp, ep, b);
@@ -339,8 +375,9 @@ static void adjoint_terms_for_atom(const odims* d, const double* G, const double
 }
 
 /* dG contributions landing on source atom b (terms whose neighbour is b). */
-static void adjoint_dG_for_atom(const odims* d, const double* D, const double* A, const int32_t* nbr,
-                                cplx alpha, const double* gS, int64_t b, double* dG, cplx* work) {
+static void adjoint_dG_for_atom(const odims* d, const double* Dp, const double* Dm, const double* A,
+                                const int32_t* nbr, cplx alpha, const double* gS, int64_t b, double* dG,
+                                cplx* work) {
     const int64_t N = d->norb, NN = N * N;
     cplx* Y = work; /* A_i^H g */
     for (int64_t a = 0; a < d->na; ++a)
@@ -355,6 +392,7 @@ static void adjoint_dG_for_atom(const odims* d, const double* D, const double* A
                             for (int s = +1; s >= -1; s -= 2) {
                                 const int64_t ep = e - s * m;
                                 if (ep < 0 || ep >= d->ne) continue;
+                                const double* D = s > 0 ? Dp : Dm;
                                 double* dB = dG + 2 * off_G(d, kp, ep, b);
                                 for (int i = 0; i < 3; ++i) {
                                     const double* Ai = A + 2 * off_A(d, a, n, i);
@@ -386,18 +424,22 @@ static void adjoint_dG_for_atom(const odims* d, const double* D, const double* A
     (void)NN;
 }
 
-int oracle_sse_backward(const int64_t* dims, const double* G, const double* D, const double* A,
-                        const int32_t* nbr, double alpha_re, double alpha_im, const double* dSigma,
-                        double* dG, double* dD, double* dA) {
+/* Adjoint over signed frequencies: gradients with respect to G, Dp, Dm and A.
+ * dDp and dDm may be the same array (then it receives both); any output may be
+ * NULL. */
+int oracle_sse_backward_signed(const int64_t* dims, const double* G, const double* Dp, const double* Dm,
+                               const double* A, const int32_t* nbr, double alpha_re, double alpha_im,
+                               const double* dSigma, double* dG, double* dDp, double* dDm, double* dA) {
     odims d;
     int rc = read_dims(dims, &d);
     if (rc) return rc;
-    if (!G || !D || !A || !nbr || !dSigma) return 1;
+    if (!G || !Dp || !Dm || !A || !nbr || !dSigma || (!dDp) != (!dDm)) return 1;
     if ((rc = check_nbr(&d, nbr))) return rc;
     const cplx alpha = { alpha_re, alpha_im };
     const int64_t NN = d.norb * d.norb;
     if (dG) memset(dG, 0, sizeof(double) * 2 * d.nkz * d.ne * d.na * d.gs * NN);
-    if (dD) memset(dD, 0, sizeof(double) * 2 * d.nqz * d.nw * d.na * d.nb * 9);
+    if (dDp) memset(dDp, 0, sizeof(double) * 2 * d.nqz * d.nw * d.na * d.nb * 9);
+    if (dDm) memset(dDm, 0, sizeof(double) * 2 * d.nqz * d.nw * d.na * d.nb * 9);
     if (dA) memset(dA, 0, sizeof(double) * 2 * d.na * d.nb * 3 * NN);
     int fail = 0;
 #pragma omp parallel
@@ -407,18 +449,26 @@ int oracle_sse_backward(const int64_t* dims, const double* G, const double* D, c
 #pragma omp atomic write
             fail = 1;
         } else {
-            if (dD || dA) {
+            if (dDp || dA) {
 #pragma omp for schedule(dynamic, 1)
-                for (int64_t a = 0; a < d.na; ++a) adjoint_terms_for_atom(&d, G, D, A, nbr, alpha, dSigma, a, dD, dA, work);
+                for (int64_t a = 0; a < d.na; ++a)
+                    adjoint_terms_for_atom(&d, G, Dp, Dm, A, nbr, alpha, dSigma, a, dDp, dDm, dA, work);
             }
             if (dG) {
 #pragma omp for schedule(dynamic, 1)
-                for (int64_t b = 0; b < d.na; ++b) adjoint_dG_for_atom(&d, D, A, nbr, alpha, dSigma, b, dG, work);
+                for (int64_t b = 0; b < d.na; ++b) adjoint_dG_for_atom(&d, Dp, Dm, A, nbr, alpha, dSigma, b, dG, work);
             }
         }
         free(work);
     }
     return fail ? 7 : 0;
+}
+
+/* The one-table form: both branches read D and feed dD. */
+int oracle_sse_backward(const int64_t* dims, const double* G, const double* D, const double* A,
+                        const int32_t* nbr, double alpha_re, double alpha_im, const double* dSigma,
+                        double* dG, double* dD, double* dA) {
+    return oracle_sse_backward_signed(dims, G, D, D, A, nbr, alpha_re, alpha_im, dSigma, dG, dD, dD, dA);
 }
 
 /*

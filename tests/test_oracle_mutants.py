@@ -125,3 +125,57 @@ def test_pse_mutant_is_caught(tmp_path, name):
     oracle.build(src=str(path), out=so)
     failed = _pse_pin_checks(oracle.Bound(so))
     assert failed, f"mutant {name} passed every pin"
+
+
+# Slips in the full Eq. 3 input contract (stored grad H_ba, adjoint over signed
+# frequencies), checked against their own pins.
+import test_oracle_f1_pins as f1_pins
+
+F1_MUTANTS = {
+    "ba_transposed": ("c_at(Y, u * N + c)", "c_at(Y, c * N + u)"),
+    "ba_conjugated": ("c_at(Y, u * N + c)", "c_conj(c_at(Y, u * N + c))"),
+    "ba_ignored": ("if (Aba)\n", "if (0)\n"),
+    "adjoint_dD_tables_swapped": ("double* dD = s > 0 ? dDp : dDm;", "double* dD = s > 0 ? dDm : dDp;"),
+    "adjoint_terms_tables_swapped": ("const double* D = s > 0 ? Dp : Dm;\n                        double* dD",
+                                     "const double* D = s > 0 ? Dm : Dp;\n                        double* dD"),
+    "adjoint_dG_tables_swapped": ("const double* D = s > 0 ? Dp : Dm;\n                                double* dB",
+                                  "const double* D = s > 0 ? Dm : Dp;\n                                double* dB"),
+}
+
+
+def _f1_pin_checks(lib):
+    failed = []
+    checks = [
+        ("explicit_hermitian", lambda: f1_pins.test_explicit_hermitian_right_factor_is_bitwise_the_default(lib)),
+        ("closed_form_a", lambda: f1_pins.test_closed_form_with_independent_right_factor(lib, 0, 1, 0, 0, 2)),
+        ("closed_form_b", lambda: f1_pins.test_closed_form_with_independent_right_factor(lib, 2, 3, 2, 1, 0)),
+        ("linear", lambda: f1_pins.test_linear_in_right_factor(lib)),
+        ("dense", lambda: f1_pins.test_right_factor_matches_dense_einsum(lib)),
+        ("adjoint_dot", lambda: f1_pins.test_signed_adjoint_dot_products(lib, 1j)),
+        ("adjoint_fd", lambda: f1_pins.test_signed_adjoint_grad_H_central_difference_exact(lib)),
+        ("adjoint_dense", lambda: f1_pins.test_signed_adjoint_matches_dense_autograd(lib)),
+        ("adjoint_one_table", lambda: f1_pins.test_signed_adjoint_reduces_to_one_table(lib)),
+    ]
+    for name, fn in checks:
+        try:
+            fn()
+        except AssertionError:
+            failed.append(name)
+    return failed
+
+
+def test_unmutated_oracle_passes_f1_pins():
+    assert _f1_pin_checks(oracle.Bound(oracle.current_lib_path())) == []
+
+
+@pytest.mark.parametrize("name", sorted(F1_MUTANTS))
+def test_f1_mutant_is_caught(tmp_path, name):
+    old, new = F1_MUTANTS[name]
+    src = open(oracle.SRC).read()
+    assert src.count(old) == 1, f"mutation site for {name} not unique"
+    path = tmp_path / f"mut_{name}.c"
+    path.write_text(src.replace(old, new))
+    so = str(tmp_path / f"libmut_{name}.so")
+    oracle.build(src=str(path), out=so)
+    failed = _f1_pin_checks(oracle.Bound(so))
+    assert failed, f"mutant {name} passed every pin"
