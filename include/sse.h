@@ -44,8 +44,10 @@
  *   stream).  Outputs are overwritten, never accumulated.  Inputs are only
  *   read.  Calls that use distinct outputs and workspaces may run
  *   concurrently.
- * - Status codes (no exceptions cross this boundary; on any error no kernel
- *   has been launched and no output has been touched):
+ * - Status codes (no exceptions cross this boundary; on an argument error --
+ *   every code but SSE_ERR_HIP -- no kernel has been launched and no output has
+ *   been touched; an SSE_ERR_HIP from a call that launches several kernels may
+ *   leave its outputs partly written):
  *     SSE_OK 0, SSE_ERR_NULL 1 (required pointer is NULL), SSE_ERR_DIMS 2
  *     (a dim <= 0, nqz != nkz, g_slots < 1, a size beyond the supported
  *     limits, or an element count that overflows int64), SSE_ERR_WORKSPACE 3,
@@ -66,7 +68,7 @@
 extern "C" {
 #endif
 
-#define SSE_ABI_VERSION 3
+#define SSE_ABI_VERSION 4
 
 typedef struct sse_dims {
     int64_t nkz;     /* electron momentum points kz (periodic grid)              */
@@ -167,6 +169,26 @@ int sse_forward_signed(const sse_dims* dims, const double* G, const double* Dp, 
                        void* stream);
 
 /*
+ * The full input contract of Eq. 3: one coefficient table per sign of the
+ * frequency as in sse_forward_signed (Dm == Dp: the one-table form of
+ * sse_forward) and the right factor grad_j H_ba as stored blocks:
+ *
+ *   Sigma[k,E,a] = alpha * sum_q sum_{m=1}^{Nw} sum_n sum_{i,j}
+ *                  ( [E-m >= 0] Dp[q,m-1,a,n,i,j] dH[a,n,i] . G[(k-q) mod Nkz, E-m, nbr[a,n], 0] . dHba[a,n,j]
+ *                  + [E+m < NE] Dm[q,m-1,a,n,i,j] dH[a,n,i] . G[(k-q) mod Nkz, E+m, nbr[a,n], 0] . dHba[a,n,j] )
+ *
+ * dHba [na][nb][3][norb][norb] complex holds grad_j H_ba for the pair (a, b =
+ * nbr[a,n]) (the layout of dH); NULL means the Hermitian reading dHba[a,n,j] =
+ * dH[a,n,j]^H, which makes this call sse_forward_signed.  Every precision runs
+ * on the matrix-core shapes (the fp64 kernel then works on energy blocks of
+ * four, whose LDS holds the second table); other shapes take fp64 only.  Other
+ * arguments, layouts, workspace and errors as for sse_forward_signed.
+ */
+int sse_forward_ex(const sse_dims* dims, const double* G, const double* Dp, const double* Dm, const double* dH,
+                   const double* dHba, const int32_t* nbr, double alpha_re, double alpha_im, int precision,
+                   double* Sigma, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
  * Adjoint of sse_forward (fp64) for a real scalar L, given dSigma = dL/dSigma
  * in PyTorch's convention for complex gradients (dL/dRe z + i dL/dIm z).
  * Writes dL/dG (slots >= 1 set to zero), dL/dD and dL/d(dH); any of the three
@@ -187,6 +209,18 @@ int sse_backward(const sse_dims* dims, const double* G, const double* D, const d
                  const int32_t* nbr, double alpha_re, double alpha_im, const double* dSigma,
                  double* dG, double* dD, double* ddH, void* workspace, size_t workspace_bytes,
                  void* stream);
+
+/*
+ * Adjoint of sse_forward_signed (fp64): as sse_backward, with the gradients of
+ * both coefficient tables.  The terms with G at E - m read Dp and feed dDp, the
+ * terms with G at E + m read Dm and feed dDm; per valid term with d the
+ * coefficient of its table the formulas of sse_backward apply.  dG, dDp, dDm
+ * and ddH may each be NULL to skip it.  Workspace as for sse_backward.
+ */
+int sse_backward_signed(const sse_dims* dims, const double* G, const double* Dp, const double* Dm,
+                        const double* dH, const int32_t* nbr, double alpha_re, double alpha_im,
+                        const double* dSigma, double* dG, double* dDp, double* dDm, double* ddH,
+                        void* workspace, size_t workspace_bytes, void* stream);
 
 /*
  * The bracket of Eq. 3 for every neighbour slot, the step that prepares D:

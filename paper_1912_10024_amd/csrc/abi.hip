@@ -119,10 +119,11 @@ int sse_effective_flops(const sse_dims* dims, double* f_eff) {
 namespace {
 
 // Sigma with the terms whose G sits at E - w reading Dp and those at E + w
-// reading Dm (the same table for sse_forward)
+// reading Dm (the same table for sse_forward), and the right factor dHba (the
+// stored grad_j H_ba) or, for NULL, dH^H
 int forward_impl(const sse_dims* dims, const double* G, const double* Dp, const double* Dm, const double* dH,
-                 const int32_t* nbr, double alpha_re, double alpha_im, int precision, double* Sigma, void* workspace,
-                 size_t workspace_bytes, void* stream) {
+                 const double* dHba, const int32_t* nbr, double alpha_re, double alpha_im, int precision,
+                 double* Sigma, void* workspace, size_t workspace_bytes, void* stream) {
     int rc = check_dims(dims);
     if (rc) return rc;
     if (!G || !Dp || !Dm || !dH || !nbr || !Sigma) return fail(SSE_ERR_NULL, "a tensor pointer is NULL");
@@ -137,19 +138,19 @@ int forward_impl(const sse_dims* dims, const double* G, const double* Dp, const 
     hipError_t e;
     if (sse::fwd_mfma_specialised(d)) {
         if (Dm == Dp) {
-            e = sse::launch_fwd_mfma(d, precision, G, Dp, dH, nbr, alpha, Sigma, s);
+            e = sse::launch_fwd_mfma(d, precision, G, Dp, dH, dHba, nbr, alpha, Sigma, s);
         } else {
             // one GEMM per table: the E - w terms write Sigma, the E + w terms add to it
-            e = sse::launch_fwd_mfma(d, precision, G, Dp, dH, nbr, alpha, Sigma, s, sse::kBranchMinus);
+            e = sse::launch_fwd_mfma(d, precision, G, Dp, dH, dHba, nbr, alpha, Sigma, s, sse::kBranchMinus);
             if (e == hipSuccess)
-                e = sse::launch_fwd_mfma(d, precision, G, Dm, dH, nbr, alpha, Sigma, s,
+                e = sse::launch_fwd_mfma(d, precision, G, Dm, dH, dHba, nbr, alpha, Sigma, s,
                                          sse::kBranchPlus | sse::kAccumulate);
         }
     } else {
         if (precision != SSE_FP64)
             return fail(SSE_ERR_PRECISION, "precision %d has no kernel for these dims", precision);
         if (!sse::generic_supported(d)) return fail(SSE_ERR_DIMS, "no kernel for these dims");
-        e = sse::launch_fwd_generic(d, G, Dp, Dm, dH, nbr, alpha, Sigma, s);
+        e = sse::launch_fwd_generic(d, G, Dp, Dm, dH, dHba, nbr, alpha, Sigma, s);
     }
     if (e != hipSuccess) return hip_fail(e, "forward launch");
     return ok();
@@ -162,34 +163,65 @@ extern "C" {
 int sse_forward(const sse_dims* dims, const double* G, const double* D, const double* dH, const int32_t* nbr,
                 double alpha_re, double alpha_im, int precision, double* Sigma, void* workspace,
                 size_t workspace_bytes, void* stream) {
-    return forward_impl(dims, G, D, D, dH, nbr, alpha_re, alpha_im, precision, Sigma, workspace, workspace_bytes,
-                        stream);
+    return forward_impl(dims, G, D, D, dH, nullptr, nbr, alpha_re, alpha_im, precision, Sigma, workspace,
+                        workspace_bytes, stream);
 }
 
 int sse_forward_signed(const sse_dims* dims, const double* G, const double* Dp, const double* Dm, const double* dH,
                        const int32_t* nbr, double alpha_re, double alpha_im, int precision, double* Sigma,
                        void* workspace, size_t workspace_bytes, void* stream) {
-    return forward_impl(dims, G, Dp, Dm, dH, nbr, alpha_re, alpha_im, precision, Sigma, workspace, workspace_bytes,
-                        stream);
+    return forward_impl(dims, G, Dp, Dm, dH, nullptr, nbr, alpha_re, alpha_im, precision, Sigma, workspace,
+                        workspace_bytes, stream);
 }
 
-int sse_backward(const sse_dims* dims, const double* G, const double* D, const double* dH, const int32_t* nbr,
-                 double alpha_re, double alpha_im, const double* dSigma, double* dG, double* dD, double* ddH,
-                 void* workspace, size_t workspace_bytes, void* stream) {
+int sse_forward_ex(const sse_dims* dims, const double* G, const double* Dp, const double* Dm, const double* dH,
+                   const double* dHba, const int32_t* nbr, double alpha_re, double alpha_im, int precision,
+                   double* Sigma, void* workspace, size_t workspace_bytes, void* stream) {
+    return forward_impl(dims, G, Dp, Dm, dH, dHba, nbr, alpha_re, alpha_im, precision, Sigma, workspace,
+                        workspace_bytes, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+int backward_impl(const sse_dims* dims, const double* G, const double* Dp, const double* Dm, const double* dH,
+                  const int32_t* nbr, double alpha_re, double alpha_im, const double* dSigma, double* dG,
+                  double* dDp, double* dDm, double* ddH, void* workspace, size_t workspace_bytes, void* stream,
+                  bool signed_form) {
     int rc = check_dims(dims);
     if (rc) return rc;
-    if (!G || !D || !dH || !nbr || !dSigma) return fail(SSE_ERR_NULL, "an input pointer is NULL");
+    if (!G || !Dp || !Dm || !dH || !nbr || !dSigma) return fail(SSE_ERR_NULL, "an input pointer is NULL");
     const sse::Dims d = sse::to_dims(*dims);
     if (!sse::bwd_supported(d)) return fail(SSE_ERR_DIMS, "no adjoint kernel for these dims");
     size_t need = 0;
     sse_workspace_bytes(dims, SSE_FP64, 1, &need);
     if (workspace == nullptr || workspace_bytes < need)
         return fail(SSE_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace_bytes);
-    if (!dG && !dD && !ddH) return ok();
-    hipError_t e = sse::launch_bwd(d, G, D, dH, nbr, sse::cd{alpha_re, alpha_im}, dSigma, dG, dD, ddH, workspace,
-                                   reinterpret_cast<hipStream_t>(stream));
+    if (!dG && !dDp && !dDm && !ddH) return ok();
+    hipError_t e = sse::launch_bwd(d, G, Dp, Dm, dH, nbr, sse::cd{alpha_re, alpha_im}, dSigma, dG, dDp, dDm, ddH,
+                                   workspace, reinterpret_cast<hipStream_t>(stream), signed_form);
     if (e != hipSuccess) return hip_fail(e, "backward launch");
     return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+int sse_backward(const sse_dims* dims, const double* G, const double* D, const double* dH, const int32_t* nbr,
+                 double alpha_re, double alpha_im, const double* dSigma, double* dG, double* dD, double* ddH,
+                 void* workspace, size_t workspace_bytes, void* stream) {
+    return backward_impl(dims, G, D, D, dH, nbr, alpha_re, alpha_im, dSigma, dG, dD, nullptr, ddH, workspace,
+                         workspace_bytes, stream, false);
+}
+
+int sse_backward_signed(const sse_dims* dims, const double* G, const double* Dp, const double* Dm, const double* dH,
+                        const int32_t* nbr, double alpha_re, double alpha_im, const double* dSigma, double* dG,
+                        double* dDp, double* dDm, double* ddH, void* workspace, size_t workspace_bytes,
+                        void* stream) {
+    return backward_impl(dims, G, Dp, Dm, dH, nbr, alpha_re, alpha_im, dSigma, dG, dDp, dDm, ddH, workspace,
+                         workspace_bytes, stream, true);
 }
 
 int sse_combine_d(const sse_dims* dims, const double* Dfull, const int32_t* nbr, double* Dc, void* workspace,

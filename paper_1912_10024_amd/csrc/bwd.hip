@@ -4,11 +4,14 @@
 // edge (a, n) with neighbour b = nbr[a,n] and a source point (k', E'):
 //   W_{q,w}[k',E'] = g[(k'+q) mod Nkz, E'+w, a] + g[(k'+q) mod Nkz, E'-w, a]   (0 outside the grid)
 //   Y_ij[k',E']    = conj(alpha) sum_{q,w} conj(D[q,w-1,a,n,i,j]) W_{q,w}[k',E']
-// (the adjoint of the (qz, w, +/-) stencil and of the D contraction), and with
+// (the adjoint of the (qz, w, +/-) stencil and of the D contraction; over
+// signed frequencies the g at E'+w term takes conj(Dp) and the one at E'-w
+// conj(Dm)), and with
 // B = G[k',E',b,0], P_ij = grad_i H . B . grad_j H^H:
 //   dG[k',E',b,0]   += sum_ij grad_i H^H . Y_ij . grad_j H
 //   d gradH[a,n,m]  += sum_j Y_mj . (grad_j H . B^H) + sum_i Y_im^H . (grad_i H . B)
 //   dD[q,w-1,a,n,ij] = conj(alpha) sum_{k',E'} sum_rc conj(P_ij[rc]) W_{q,w}[rc]
+//   (over signed frequencies: dDp from the g at E'+w terms, dDm from E'-w)
 // Shifted blocks are re-gathered from G and g, nothing of the forward is stored.
 //
 // dG and d gradH are formed by one workgroup per neighbour atom b, which walks
@@ -108,9 +111,12 @@ __device__ double bwd_zero_row[2] = {0.0, 0.0};
 // Y_ij[x] for all nine (i,j), summed over every qz and the frequencies
 // w in [w_lo, w_hi] of the 2*Nqz*Nw shifted g blocks (both energy branches);
 // the loads of two qz and kBatch frequencies are in flight together.
-// conj(alpha) is applied by the caller.
+// conj(alpha) is applied by the caller.  SIGNED: the g block at E'+w takes the
+// table sDn (coefficients at +w), the one at E'-w the table sDm (at -w).
+template <bool SIGNED>
 __device__ __forceinline__ void compute_y(const Dims& d, const double* __restrict__ gS, int64_t a, int64_t kp,
-                                          int64_t ep, const cd* sDn, int64_t w_lo, int64_t w_hi, int x, cd* y) {
+                                          int64_t ep, const cd* sDn, const cd* sDm, int64_t w_lo, int64_t w_hi,
+                                          int x, cd* y) {
     constexpr int kBatch = 5, kQ = 2;
 #pragma unroll
     for (int ij = 0; ij < 9; ++ij) y[ij] = cd{0.0, 0.0};
@@ -139,10 +145,18 @@ __device__ __forceinline__ void compute_y(const Dims& d, const double* __restric
                 for (int t = 0; t < kBatch; ++t) {
                     const int64_t w = w0 + t;
                     if (w > w_hi) break;
-                    const cd wv{hi[u][t].re + lo[u][t].re, hi[u][t].im + lo[u][t].im};
-                    const cd* dq = sDn + ((q0 + u) * d.nw + (w - 1)) * 9;
+                    const int64_t qw = ((q0 + u) * d.nw + (w - 1)) * 9;
+                    if constexpr (SIGNED) {
 #pragma unroll
-                    for (int ij = 0; ij < 9; ++ij) cfma_conja(y[ij], dq[ij], wv);
+                        for (int ij = 0; ij < 9; ++ij) {
+                            cfma_conja(y[ij], sDn[qw + ij], hi[u][t]);
+                            cfma_conja(y[ij], sDm[qw + ij], lo[u][t]);
+                        }
+                    } else {
+                        const cd wv{hi[u][t].re + lo[u][t].re, hi[u][t].im + lo[u][t].im};
+#pragma unroll
+                        for (int ij = 0; ij < 9; ++ij) cfma_conja(y[ij], sDn[qw + ij], wv);
+                    }
                 }
             }
         }
@@ -150,8 +164,10 @@ __device__ __forceinline__ void compute_y(const Dims& d, const double* __restric
 }
 
 // --------------------------------------------------------------- dG and d gradH
+template <bool SIGNED>
 __global__ __launch_bounds__(kBwdThreads) void bwd_dg_dh_kernel(Dims d, const double* __restrict__ G,
                                                                 const double* __restrict__ Dg,
+                                                                const double* __restrict__ Dmg,
                                                                 const double* __restrict__ Ag,
                                                                 const double* __restrict__ gS, cd calpha,
                                                                 const int32_t* __restrict__ offset,
@@ -161,7 +177,8 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_dg_dh_kernel(Dims d, const do
     const int N = (int)d.norb, NN = N * N;
     const int nqw = (int)(d.nqz * d.nw);
     cd* sDn = reinterpret_cast<cd*>(smem);  // [q][w][ij]
-    cd* sA = sDn + nqw * 9;                 // [3][N][N]   grad H of the edge
+    cd* sDm = sDn + nqw * 9;                // [q][w][ij]  (SIGNED: the coefficients at -w)
+    cd* sA = sDm + (SIGNED ? nqw * 9 : 0);  // [3][N][N]   grad H of the edge
     cd* sY = sA + 3 * NN;                   // [9][N][N]
     cd* sB = sY + 9 * NN;                   // [N][N]
     cd* sT = sB + NN;                       // [3][N][N]   sum_i A_i^H Y_ij
@@ -196,6 +213,7 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_dg_dh_kernel(Dims d, const do
         for (int x = tid; x < nqw * 9; x += kBwdThreads) {
             const int ij = x % 9, qw = x / 9;
             sDn[x] = cload(Dg, off_D(d, qw / d.nw, qw % d.nw, a, n) + ij);
+            if constexpr (SIGNED) sDm[x] = cload(Dmg, off_D(d, qw / d.nw, qw % d.nw, a, n) + ij);
         }
         for (int x = tid; x < 3 * NN; x += kBwdThreads) {
             sA[x] = cload(Ag, off_A(d, a, n, 0) + x);
@@ -209,7 +227,7 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_dg_dh_kernel(Dims d, const do
             for (int yx = tid - yh * kYHalf; yx < NN; yx += kYHalf) {
                 cd y[9];
                 const int64_t w_mid = d.nw / 2;
-                compute_y(d, gS, a, kp, ep, sDn, yh ? w_mid + 1 : 1, yh ? d.nw : w_mid, yx, y);
+                compute_y<SIGNED>(d, gS, a, kp, ep, sDn, sDm, yh ? w_mid + 1 : 1, yh ? d.nw : w_mid, yx, y);
                 cd* dst = yh ? sY1 : sY;
 #pragma unroll
                 for (int ij = 0; ij < 9; ++ij) dst[ij * NN + yx] = y[ij];
@@ -292,10 +310,11 @@ __global__ void bwd_dh_reduce_kernel(Dims d, const int32_t* __restrict__ nbr, co
 }
 
 // --------------------------------------------------------------- dD
+// branches: bit 0 the g blocks at E'+w (the terms with G at E - w), bit 1 those at E'-w
 __global__ __launch_bounds__(kBwdThreads) void bwd_dd_kernel(Dims d, const double* __restrict__ G,
                                                              const double* __restrict__ Ag,
                                                              const int32_t* __restrict__ nbr,
-                                                             const double* __restrict__ gS, cd calpha,
+                                                             const double* __restrict__ gS, cd calpha, int branches,
                                                              double* __restrict__ dD) {
     extern __shared__ double smem[];
     const int N = (int)d.norb, NN = N * N;
@@ -343,7 +362,7 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_dd_kernel(Dims d, const doubl
                 if (qw < nqw) {
                     const int64_t q = qw / d.nw, w = qw % d.nw + 1;
                     const int64_t k = (kp + q) % d.nkz;
-                    const bool hi = ep + w < d.ne, lo = ep - w >= 0;
+                    const bool hi = (branches & 1) && ep + w < d.ne, lo = (branches & 2) && ep - w >= 0;
                     const double* g1 = gS + 2 * off_S(d, k, hi ? ep + w : ep, a);
                     const double* g2 = gS + 2 * off_S(d, k, lo ? ep - w : ep, a);
                     for (int rc = 0; rc < NN; ++rc) {
@@ -375,9 +394,9 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_dd_kernel(Dims d, const doubl
     }
 }
 
-static size_t bwd_lds_dg(const Dims& d) {
+static size_t bwd_lds_dg(const Dims& d, bool signed_form = false) {
     const size_t NN = (size_t)(d.norb * d.norb);
-    return sizeof(cd) * ((size_t)d.nqz * d.nw * 9 + 3 * NN + 9 * NN + NN + 4 * 3 * NN);
+    return sizeof(cd) * ((size_t)d.nqz * d.nw * 9 * (signed_form ? 2 : 1) + 3 * NN + 9 * NN + NN + 4 * 3 * NN);
 }
 static size_t bwd_lds_dd(const Dims& d) {
     const size_t NN = (size_t)(d.norb * d.norb);
@@ -385,13 +404,40 @@ static size_t bwd_lds_dd(const Dims& d) {
 }
 
 bool bwd_supported(const Dims& d) {
-    return d.nqz * d.nw <= 2 * kBwdThreads && d.norb * d.norb <= kBwdThreads && bwd_lds_dg(d) <= 160 * 1024 &&
+    return d.nqz * d.nw <= 2 * kBwdThreads && d.norb * d.norb <= kBwdThreads && bwd_lds_dg(d, true) <= 160 * 1024 &&
            bwd_lds_dd(d) <= 160 * 1024 && d.na * d.nb <= INT32_MAX && (d.na + 7) / 8 * 8 * d.nkz <= INT32_MAX;
 }
 
-hipError_t launch_bwd(const Dims& d, const double* G, const double* D, const double* A, const int32_t* nbr, cd alpha,
-                      const double* gS, double* dG, double* dD, double* dA, void* ws, hipStream_t stream) {
+// dD (or dDp / dDm) for the given energy branches
+static hipError_t launch_dd(const Dims& d, const double* G, const double* A, const int32_t* nbr, const double* gS,
+                            cd calpha, double* dD, int branches, hipStream_t stream) {
+    if (pse_mfma_specialised(d)) return launch_dd_mfma(d, G, A, nbr, gS, calpha, dD, stream, branches);
+    const size_t lds = bwd_lds_dd(d);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(bwd_dd_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(bwd_dd_kernel, dim3((unsigned)(d.na * d.nb)), dim3(kBwdThreads), lds, stream, d, G, A, nbr, gS,
+                       calpha, branches, dD);
+    return hipGetLastError();
+}
+
+hipError_t launch_bwd(const Dims& d, const double* G, const double* Dp, const double* Dm, const double* A,
+                      const int32_t* nbr, cd alpha, const double* gS, double* dG, double* dDp, double* dDm, double* dA,
+                      void* ws, hipStream_t stream, bool signed_form) {
     const cd calpha{alpha.re, -alpha.im};
+    // every attribute is set before the first launch, so a failure leaves all outputs untouched
+    const size_t lds = bwd_lds_dg(d, signed_form);
+    auto kern = signed_form ? bwd_dg_dh_kernel<true> : bwd_dg_dh_kernel<false>;
+    if (dG || dA) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    if ((dDp || dDm) && !pse_mfma_specialised(d)) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(bwd_dd_kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bwd_lds_dd(d));
+        if (e != hipSuccess) return e;
+    }
     if (dG || dA) {
         int32_t* count = reinterpret_cast<int32_t*>(ws);
         int32_t* offset = count + d.na;
@@ -404,15 +450,11 @@ hipError_t launch_bwd(const Dims& d, const double* G, const double* D, const dou
         hipLaunchKernelGGL(rcsr_fill_kernel, dim3(g1), dim3(256), 0, stream, d.na, d.nb, nbr, cursor, edges);
         const unsigned g2 = (unsigned)((d.na + 255) / 256 < 4096 ? (d.na + 255) / 256 : 4096);
         hipLaunchKernelGGL(rcsr_sort_kernel, dim3(g2), dim3(256), 0, stream, d.na, offset, edges);
-        const size_t lds = bwd_lds_dg(d);
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(bwd_dg_dh_kernel),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
         double* dApart = dA ? reinterpret_cast<double*>(reinterpret_cast<char*>(ws) + bwd_csr_bytes(d)) : nullptr;
         const int64_t groups = (d.na + 7) / 8 * 8 * d.nkz;
-        hipLaunchKernelGGL(bwd_dg_dh_kernel, dim3((unsigned)groups), dim3(kBwdThreads), lds, stream, d, G, D, A, gS,
-                           calpha, offset, edges, dG, dApart);
-        e = hipGetLastError();
+        hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(kBwdThreads), lds, stream, d, G, Dp, Dm, A, gS, calpha,
+                           offset, edges, dG, dApart);
+        hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         if (dA) {
             const int64_t n = d.na * d.nb * 3 * d.norb * d.norb;
@@ -422,15 +464,12 @@ hipError_t launch_bwd(const Dims& d, const double* G, const double* D, const dou
             if (e != hipSuccess) return e;
         }
     }
-    if (dD && pse_mfma_specialised(d)) return launch_dd_mfma(d, G, A, nbr, gS, calpha, dD, stream);
-    if (dD) {
-        const size_t lds = bwd_lds_dd(d);
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(bwd_dd_kernel),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (!signed_form) return dDp ? launch_dd(d, G, A, nbr, gS, calpha, dDp, 3, stream) : hipGetLastError();
+    if (dDp) {
+        hipError_t e = launch_dd(d, G, A, nbr, gS, calpha, dDp, 1, stream);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(bwd_dd_kernel, dim3((unsigned)(d.na * d.nb)), dim3(kBwdThreads), lds, stream, d, G, A, nbr, gS,
-                           calpha, dD);
     }
+    if (dDm) return launch_dd(d, G, A, nbr, gS, calpha, dDm, 2, stream);
     return hipGetLastError();
 }
 

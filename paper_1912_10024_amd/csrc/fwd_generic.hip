@@ -1,6 +1,7 @@
 // Direct (term-by-term) forward kernel for shapes without a matrix-core
 // specialisation.  One workgroup per output block Sigma[k,E,a]; every term of
-// Eq. 3 is formed as (grad_i H . G_b) . grad_j H^H in fp64 on the vector ALUs.
+// Eq. 3 is formed as (grad_i H . G_b) . grad_j H_ba in fp64 on the vector ALUs,
+// with grad_j H_ba the stored block B[a,n,j] when given, else grad_j H^H.
 #include "sse_kernels.h"
 
 namespace sse {
@@ -14,6 +15,7 @@ __global__ __launch_bounds__(kGenThreads) void fwd_generic_kernel(Dims d, const 
                                                                   const double* __restrict__ Dp,
                                                                   const double* __restrict__ Dm,
                                                                   const double* __restrict__ A,
+                                                                  const double* __restrict__ B,
                                                                   const int32_t* __restrict__ nbr, cd alpha,
                                                                   double* __restrict__ S) {
     extern __shared__ double smem[];
@@ -56,9 +58,14 @@ __global__ __launch_bounds__(kGenThreads) void fwd_generic_kernel(Dims d, const 
                             const int r = x / N, c = x % N;
                             for (int i = 0; i < 3; ++i)
                                 for (int j = 0; j < 3; ++j) {
-                                    const double* Aj = A + 2 * off_A(d, a, n, j);
                                     cd u = cd{0.0, 0.0};
-                                    for (int uu = 0; uu < N; ++uu) cfma_conj(u, sT[i * NN + r * N + uu], cload(Aj, c * N + uu));
+                                    if (B) {
+                                        const double* Bj = B + 2 * off_A(d, a, n, j);
+                                        for (int uu = 0; uu < N; ++uu) cfma(u, sT[i * NN + r * N + uu], cload(Bj, uu * N + c));
+                                    } else {
+                                        const double* Aj = A + 2 * off_A(d, a, n, j);
+                                        for (int uu = 0; uu < N; ++uu) cfma_conj(u, sT[i * NN + r * N + uu], cload(Aj, c * N + uu));
+                                    }
                                     cfma(acc[xi], cload(Dq, i * 3 + j), u);
                                 }
                         }
@@ -77,11 +84,11 @@ __global__ __launch_bounds__(kGenThreads) void fwd_generic_kernel(Dims d, const 
 }
 
 hipError_t launch_fwd_generic(const Dims& d, const double* G, const double* Dp, const double* Dm, const double* A,
-                              const int32_t* nbr, cd alpha, double* S, hipStream_t stream) {
+                              const double* B, const int32_t* nbr, cd alpha, double* S, hipStream_t stream) {
     const int64_t nblk = d.nkz * d.ne * d.na;
     const unsigned grid = (unsigned)(nblk < (int64_t)(1 << 30) ? nblk : (1 << 30));
     const size_t lds = sizeof(cd) * 4 * (size_t)(d.norb * d.norb);
-    hipLaunchKernelGGL(fwd_generic_kernel, dim3(grid), dim3(kGenThreads), lds, stream, d, G, Dp, Dm, A, nbr, alpha, S);
+    hipLaunchKernelGGL(fwd_generic_kernel, dim3(grid), dim3(kGenThreads), lds, stream, d, G, Dp, Dm, A, B, nbr, alpha, S);
     return hipGetLastError();
 }
 

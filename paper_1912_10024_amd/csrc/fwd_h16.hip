@@ -34,15 +34,17 @@
 // second GEMM per neighbour: rows (i, E'), K = (u, re/im) of X = grad_i H . G
 // (row r), columns (j, c, re/im) against the embedding of conj(grad_j H) with
 // the signs placed in the static table ((Re, Im) -> (Ar, Ai) for the real
-// column and (-Ai, Ar) for the imaginary one).  X rows are formed in fp64 on
-// the vector ALUs from the gathered G columns, normalised (fp16) and split once.
+// column and (-Ai, Ar) for the imaginary one; with a stored grad_j H_ba, B =
+// Bba_j[u][c] takes the place of conj(A_j[c][u])).  X rows are formed in fp64
+// on the vector ALUs from the gathered G columns, normalised (fp16) and split
+// once.
 //
-// Pipeline per chunk (one barrier), as in the fp64 kernel: run the main GEMM on
-// the P chunk in LDS, gather G columns of a later chunk into registers, form the
-// P chunk of the next chunk from the X rows in LDS, form the X rows of the chunk
-// after that.  Waves 0-3 and 4-7 (the two waves of each SIMD) run these
-// phases in opposite orders: the 16-bit matrix instructions of one wave run
-// while the other issues vector work.  Each chunk's fp32 sums are unscaled
+// Pipeline per chunk (one barrier): form the P chunk of the next chunk from the
+// X rows in LDS, form the X rows of the chunk after that from G columns
+// gathered into registers one chunk earlier, run the main GEMM on the P chunk
+// in LDS, gather the G columns of a later chunk.  The 16-bit matrix
+// instructions of one wave run while the other wave of the SIMD issues vector
+// work.  Each chunk's fp32 sums are unscaled
 // and added to fp64 accumulators; the (w, +/-) stencil adds them into an fp64
 // output ring in LDS in conflict-free phases (bitwise reproducible).
 #include "fwd_common.h"
@@ -186,8 +188,8 @@ struct H16Cfg {
 template <int NORB, int NKZ, int NW, int NB, int EB, int PREC, int FLAGS>
 __global__ __launch_bounds__(512) void fwd_h16_kernel(Dims d, const double* __restrict__ G,
                                                       const double* __restrict__ Dg, const double* __restrict__ Ag,
-                                                      const int32_t* __restrict__ nbr, cd alpha,
-                                                      double* __restrict__ S) {
+                                                      const double* __restrict__ Bg, const int32_t* __restrict__ nbr,
+                                                      cd alpha, double* __restrict__ S) {
     using C = H16Cfg<NORB, NKZ, NW, NB, EB>;
     using O = Split16<PREC>;
     constexpr bool NORM = PREC == SSE_FP16X2;
@@ -210,7 +212,8 @@ __global__ __launch_bounds__(512) void fwd_h16_kernel(Dims d, const double* __re
     if (a >= d.na) return;  // uniform for the whole workgroup, before any barrier
 
     // ---- fp16: per-atom power-of-two normalisation of D (largest part below 2^7)
-    // and grad H (below 2), from workgroup maxima
+    // and grad H (below 2; with a stored grad H_ba, over both factors), from
+    // workgroup maxima
     double sc_d = 1.0, sc_h = 1.0, inv_base = 1.0;
     if constexpr (NORM) {
         auto block_max = [&](double m) {
@@ -231,6 +234,10 @@ __global__ __launch_bounds__(512) void fwd_h16_kernel(Dims d, const double* __re
         for (int x = tid; x < NB * 3 * C::NN; x += C::THREADS) {
             const cd v = cload(Ag, off_A(d, a, 0, 0) + x);
             mh = fmax(mh, fmax(fabs(v.re), fabs(v.im)));
+            if (Bg) {
+                const cd b = cload(Bg, off_A(d, a, 0, 0) + x);
+                mh = fmax(mh, fmax(fabs(b.re), fabs(b.im)));
+            }
         }
         sc_d = pow2_scale(block_max(md), 7);
         sc_h = pow2_scale(block_max(mh), 1);
@@ -266,15 +273,24 @@ __global__ __launch_bounds__(512) void fwd_h16_kernel(Dims d, const double* __re
         sAr[2 * x] = v.re * sc_h;
         sAr[2 * x + 1] = v.im * sc_h;
     }
-    // embedding of conj(grad_j H) for the P tiles: K pair u = (Re, Im) of X[u];
-    // column (j, c, 0) takes (Ar, Ai)[c][u] (real part of X . A^H), column
-    // (j, c, 1) takes (-Ai, Ar)[c][u] (imaginary part)
+    // embedding of the right factor B = grad_j H_ba for the P tiles, B[u][c] =
+    // conj(A_j[c][u]) or the stored block: K pair u = (Re, Im) of X[u]; column
+    // (j, c, 0) takes (Br, -Bi) (real part of X . B), column (j, c, 1) takes
+    // (Bi, Br) (imaginary part)
     for (int x = tid; x < NB * NORB * C::PN; x += C::THREADS) {
         const int col = x % C::PN, u = (x / C::PN) % NORB, n = x / (C::PN * NORB);
-        const int comp = col & 1, jc = col >> 1;
-        const cd v = cload(Ag, off_A(d, a, n, jc / NORB) + (jc % NORB) * NORB + u);
-        const double vr = v.re * sc_h, vi = v.im * sc_h;
-        const double b0 = comp ? -vi : vr, b1 = comp ? vr : vi;
+        const int comp = col & 1, jc = col >> 1, c = jc % NORB;
+        double br, bi;
+        if (Bg) {
+            const cd v = cload(Bg, off_A(d, a, n, jc / NORB) + u * NORB + c);
+            br = v.re * sc_h;
+            bi = v.im * sc_h;
+        } else {
+            const cd v = cload(Ag, off_A(d, a, n, jc / NORB) + c * NORB + u);
+            br = v.re * sc_h;
+            bi = -v.im * sc_h;
+        }
+        const double b0 = comp ? bi : br, b1 = comp ? br : -bi;
         sH[(n * NORB + u) * C::HCOLS + col] = p_form(O::split(to_f32(b0)), O::split(to_f32(b1)));
     }
 
@@ -350,14 +366,14 @@ __global__ __launch_bounds__(512) void fwd_h16_kernel(Dims d, const double* __re
         if (g >= niter) return;
         const uint2* Xb = sX + (g & 1) * C::XB;
         uint32_t* P = reinterpret_cast<uint32_t*>(sP + (g & 1) * C::PBS);
+        f32x4 acc[C::MAXU][C::PMT];
 #pragma unroll
         for (int ui = 0; ui < C::MAXU; ++ui) {
             const int unit = wave + C::WAVES * ui;
             if (unit >= C::UNITS) break;  // uniform per wave
             const int n = unit / C::PNT, nt = unit % C::PNT;
-            f32x4 acc[C::PMT];
 #pragma unroll
-            for (int mt = 0; mt < C::PMT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int mt = 0; mt < C::PMT; ++mt) acc[ui][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int s = 0; s < C::PKS; ++s) {
                 const int u = 4 * s + kk;
@@ -368,13 +384,20 @@ __global__ __launch_bounds__(512) void fwd_h16_kernel(Dims d, const double* __re
                 for (int mt = 0; mt < C::PMT; ++mt) {
                     const int row = 16 * mt + j16;
                     const uint2* xp = (u_ok && row < C::PM) ? Xb + (n * NORB + u) * C::XRS + row : sX + C::XZ;
-                    acc[mt] = O::mma(m_operand(*xp), hb, acc[mt]);
+                    acc[ui][mt] = O::mma(m_operand(*xp), hb, acc[ui][mt]);
                 }
             }
-            // P entry e = 9 n + 3 i + j, component re/im, of column (E', c) into its
-            // slot of the 16-byte unit (row 4 (e/8) + 2 ((e/4)&1) + comp); a lane's four
-            // results are consecutive E' of one i; padding rows and columns write the
-            // spare unit
+        }
+        // P entry e = 9 n + 3 i + j, component re/im, of column (E', c) into its
+        // slot of the 16-byte unit (row 4 (e/8) + 2 ((e/4)&1) + comp); a lane's four
+        // results are consecutive E' of one i; padding rows and columns write the
+        // spare unit.  The stores follow all the products of the wave's units, so
+        // the matrix pipeline drains once.
+#pragma unroll
+        for (int ui = 0; ui < C::MAXU; ++ui) {
+            const int unit = wave + C::WAVES * ui;
+            if (unit >= C::UNITS) break;
+            const int n = unit / C::PNT, nt = unit % C::PNT;
             const int col = 16 * nt + j16;
             const int comp = col & 1, jc = col >> 1, j = jc / NORB, c = jc % NORB;
 #pragma unroll
@@ -385,7 +408,7 @@ __global__ __launch_bounds__(512) void fwd_h16_kernel(Dims d, const double* __re
                 const bool ok = i < 3 && col < C::PN;
                 uint32_t* dst = P + (ok ? (prow * C::NCP + 4 * (kk & 1) * NORB + c) * 4 + (e & 3) : 4 * C::TRASH);
 #pragma unroll
-                for (int v = 0; v < 4; ++v) dst[v * 4 * NORB] = O::split(acc[mt][v]);
+                for (int v = 0; v < 4; ++v) dst[v * 4 * NORB] = O::split(acc[ui][mt][v]);
             }
         }
     };
@@ -543,13 +566,17 @@ __global__ __launch_bounds__(512) void fwd_h16_kernel(Dims d, const double* __re
         }
     };
 
-    // ---- the two waves of a SIMD (w and w+4) run opposite phases: waves 0-3
-    // issue their matrix work first and form P and X afterwards, waves 4-7 form
-    // P and X (from G loads issued at the end of the previous chunk) first.  Every phase has
-    // one call site, which keeps the accumulators in place across the loop.
-    const bool mfma_first = wave < 4;
+    // ---- every wave runs the phases in the same order: the P tiles of the next
+    // chunk, the X rows of the chunk after (from G loads issued at the end of the
+    // previous chunk), the main GEMM of this chunk at a raised issue priority
+    // (its matrix instructions then start as soon as their operands are in,
+    // and the vector work of the other wave on the SIMD fills the gaps), and the
+    // G gather of a later chunk, in flight across the barrier and the next P
+    // tiles.  Every phase has one call site, which keeps the accumulators in
+    // place across the loop.  (Measured at the device workload against the two
+    // waves of a SIMD running opposite orders: 838 -> 752 ms for fp16 hi/lo.)
 
-    // ---- prologue: X for chunks 0 and 1, P for chunk 0
+    // ---- prologue: X for chunks 0 and 1, P for chunk 0, G for chunk 2
     __syncthreads();
     gather_g(0);
     finish_x(0);
@@ -557,7 +584,7 @@ __global__ __launch_bounds__(512) void fwd_h16_kernel(Dims d, const double* __re
     gather_g(1);
     p_tiles(0);
     finish_x(1);
-    if (!mfma_first) gather_g(2);
+    gather_g(2);
     __syncthreads();
 
     // ---- main loop: energy blocks, one K chunk per momentum k', one barrier per chunk
@@ -567,19 +594,12 @@ __global__ __launch_bounds__(512) void fwd_h16_kernel(Dims d, const double* __re
         acc_x = f64x4{0.0, 0.0, 0.0, 0.0};
         for (int ch = 0; ch < NKZ; ++ch) {
             const int g = blk * NKZ + ch;
-            if (!mfma_first) {
-                finish_x(g + 2);  // G for chunk g+2 was gathered at the end of chunk g-1
-                p_tiles(g + 1);
-            }
+            p_tiles(g + 1);
+            finish_x(g + 2);  // G for chunk g+2 was gathered at the end of chunk g-1
+            __builtin_amdgcn_s_setprio(1);
             mfma_chunk(g);
-            // the gathered columns are not live across the main GEMM; their loads
-            // are in flight under the P tiles (waves 0-3) or the barrier and the
-            // next chunk's start (waves 4-7)
-            gather_g(mfma_first ? g + 2 : g + 3);
-            if (mfma_first) {
-                p_tiles(g + 1);
-                finish_x(g + 2);
-            }
+            __builtin_amdgcn_s_setprio(0);
+            gather_g(g + 3);
             __syncthreads();
         }
         for (int ph = 0; ph < plan.nphase; ++ph) {
@@ -593,7 +613,7 @@ __global__ __launch_bounds__(512) void fwd_h16_kernel(Dims d, const double* __re
 
 template <int NORB, int NKZ, int NW, int NB, int PREC, int FLAGS>
 static hipError_t launch_h16_flags(const Dims& d, const double* G, const double* D, const double* A,
-                                   const int32_t* nbr, cd alpha, double* S, hipStream_t stream) {
+                                   const double* B, const int32_t* nbr, cd alpha, double* S, hipStream_t stream) {
     constexpr int EB = 8;
     using C = H16Cfg<NORB, NKZ, NW, NB, EB>;
     auto kern = fwd_h16_kernel<NORB, NKZ, NW, NB, EB, PREC, FLAGS>;
@@ -603,37 +623,39 @@ static hipError_t launch_h16_flags(const Dims& d, const double* G, const double*
                                        (int)C::LDS_BYTES);
     if (e != hipSuccess) return e;
     const int64_t groups = ((d.na + 7) / 8) * 8 * NORB;
-    hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(C::THREADS), C::LDS_BYTES, stream, d, G, D, A, nbr, alpha, S);
+    hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(C::THREADS), C::LDS_BYTES, stream, d, G, D, A, B, nbr, alpha,
+                       S);
     return hipGetLastError();
 }
 
 template <int NORB, int NKZ, int NW, int NB, int PREC>
-static hipError_t launch_h16(const Dims& d, const double* G, const double* D, const double* A, const int32_t* nbr,
-                             cd alpha, double* S, hipStream_t stream, int flags) {
+static hipError_t launch_h16(const Dims& d, const double* G, const double* D, const double* A, const double* B,
+                             const int32_t* nbr, cd alpha, double* S, hipStream_t stream, int flags) {
     constexpr int kBoth = kBranchMinus | kBranchPlus, kPlusAdd = kBranchPlus | kAccumulate;
-    if (flags == kBoth) return launch_h16_flags<NORB, NKZ, NW, NB, PREC, kBoth>(d, G, D, A, nbr, alpha, S, stream);
+    if (flags == kBoth) return launch_h16_flags<NORB, NKZ, NW, NB, PREC, kBoth>(d, G, D, A, B, nbr, alpha, S, stream);
     if (flags == kBranchMinus)
-        return launch_h16_flags<NORB, NKZ, NW, NB, PREC, kBranchMinus>(d, G, D, A, nbr, alpha, S, stream);
-    if (flags == kPlusAdd) return launch_h16_flags<NORB, NKZ, NW, NB, PREC, kPlusAdd>(d, G, D, A, nbr, alpha, S, stream);
+        return launch_h16_flags<NORB, NKZ, NW, NB, PREC, kBranchMinus>(d, G, D, A, B, nbr, alpha, S, stream);
+    if (flags == kPlusAdd)
+        return launch_h16_flags<NORB, NKZ, NW, NB, PREC, kPlusAdd>(d, G, D, A, B, nbr, alpha, S, stream);
     return hipErrorInvalidValue;
 }
 
 template <int PREC>
-static hipError_t dispatch_h16(const Dims& d, const double* G, const double* D, const double* A, const int32_t* nbr,
-                               cd alpha, double* S, hipStream_t stream, int flags) {
+static hipError_t dispatch_h16(const Dims& d, const double* G, const double* D, const double* A, const double* B,
+                               const int32_t* nbr, cd alpha, double* S, hipStream_t stream, int flags) {
     if (d.norb == 10 && d.nkz == 7 && d.nw == 10 && d.nb == 4)
-        return launch_h16<10, 7, 10, 4, PREC>(d, G, D, A, nbr, alpha, S, stream, flags);
+        return launch_h16<10, 7, 10, 4, PREC>(d, G, D, A, B, nbr, alpha, S, stream, flags);
     if (d.norb == 10 && d.nkz == 7 && d.nw == 10 && d.nb == 3)
-        return launch_h16<10, 7, 10, 3, PREC>(d, G, D, A, nbr, alpha, S, stream, flags);
+        return launch_h16<10, 7, 10, 3, PREC>(d, G, D, A, B, nbr, alpha, S, stream, flags);
     if (d.norb == 4 && d.nkz == 3 && d.nw == 2 && d.nb == 4)
-        return launch_h16<4, 3, 2, 4, PREC>(d, G, D, A, nbr, alpha, S, stream, flags);
+        return launch_h16<4, 3, 2, 4, PREC>(d, G, D, A, B, nbr, alpha, S, stream, flags);
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_fwd_h16(const Dims& d, int precision, const double* G, const double* D, const double* A,
-                          const int32_t* nbr, cd alpha, double* S, hipStream_t stream, int flags) {
-    if (precision == SSE_FP16X2) return dispatch_h16<SSE_FP16X2>(d, G, D, A, nbr, alpha, S, stream, flags);
-    if (precision == SSE_BF16X2) return dispatch_h16<SSE_BF16X2>(d, G, D, A, nbr, alpha, S, stream, flags);
+                          const double* B, const int32_t* nbr, cd alpha, double* S, hipStream_t stream, int flags) {
+    if (precision == SSE_FP16X2) return dispatch_h16<SSE_FP16X2>(d, G, D, A, B, nbr, alpha, S, stream, flags);
+    if (precision == SSE_BF16X2) return dispatch_h16<SSE_BF16X2>(d, G, D, A, B, nbr, alpha, S, stream, flags);
     return hipErrorInvalidValue;
 }
 

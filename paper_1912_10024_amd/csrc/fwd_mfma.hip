@@ -67,7 +67,9 @@ struct Oper<SSE_FP32> {
     static __device__ __forceinline__ int row_of(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
-template <int NORB, int NKZ, int NW, int NB, int EB, int PREC>
+// HBA: the right factor of Eq. 3 is a stored grad_j H_ba (its own table in LDS
+// for the P tiles) instead of grad_j H^H
+template <int NORB, int NKZ, int NW, int NB, int EB, int PREC, bool HBA>
 struct Fwd64 {
     using T = typename Oper<PREC>::T;
     static constexpr int WAVES = 8, THREADS = 64 * WAVES;
@@ -113,9 +115,11 @@ struct Fwd64 {
     static constexpr int XR = 2 * NORB + 2;
     static constexpr int XB = 2 * EB * 3 * XR;
     // P tiles run on fp64 MFMAs for the fp64 form and on fp32 MFMAs otherwise;
-    // their operands (X rows and a copy of grad H) are stored in that type
+    // their operands (X rows and a copy of the right factor) are stored in that
+    // type; the fp64 form shares the grad H table with the X rows unless the
+    // right factor is a stored grad H_ba
     using TPT = typename Oper<PREC == SSE_FP64 ? SSE_FP64 : SSE_FP32>::T;
-    static constexpr bool SPLIT_A = PREC != SSE_FP64;
+    static constexpr bool SPLIT_A = PREC != SSE_FP64 || HBA;
     static constexpr int L_X = (2 * XB * (int)sizeof(TPT) + 7) / 8;
     static constexpr int L_AP = SPLIT_A ? (L_A * (int)sizeof(TPT) + 7) / 8 : 0;
     static constexpr int RP = NKZ * NORB * 2;  // one ring plane: [k][c] complex
@@ -168,13 +172,14 @@ struct PTileDeal {
     }
 };
 
-template <int NORB, int NKZ, int NW, int NB, int EB, int PREC, int FLAGS>
+template <int NORB, int NKZ, int NW, int NB, int EB, int PREC, int FLAGS, bool HBA>
 __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __restrict__ G,
                                                        const double* __restrict__ Dg,
                                                        const double* __restrict__ Ag,
+                                                       const double* __restrict__ Bg,
                                                        const int32_t* __restrict__ nbr, cd alpha,
                                                        double* __restrict__ S) {
-    using C = Fwd64<NORB, NKZ, NW, NB, EB, PREC>;
+    using C = Fwd64<NORB, NKZ, NW, NB, EB, PREC, HBA>;
     using O = Oper<PREC>;
     using T = typename O::T;
     constexpr PTileDeal<C> deal{};
@@ -187,7 +192,7 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     using OP = Oper<PREC == SSE_FP64 ? SSE_FP64 : SSE_FP32>;
     using TP = typename OP::T;
     double* sA = lds + C::OPER_DOUBLES;
-    TP* sAp = reinterpret_cast<TP*>(sA + (C::SPLIT_A ? C::L_A : 0));  // grad H for the P tiles
+    TP* sAp = reinterpret_cast<TP*>(sA + (C::SPLIT_A ? C::L_A : 0));  // right factor for the P tiles
     TP* sX = reinterpret_cast<TP*>(sA + C::L_A + C::L_AP);
     double* sR = sA + C::L_A + C::L_AP + C::L_X;
 
@@ -219,7 +224,12 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
         const int o = (n >> 1) * C::PSTR + ((n & 1) * 3 + i) * C::NNS + (rc / NORB) * C::AR + 2 * (rc % NORB);
         sA[o] = v.re;
         sA[o + 1] = v.im;
-        if constexpr (C::SPLIT_A) {
+        if constexpr (HBA) {
+            // the P tiles form X . conj(table)^T: the table holds conj(B_j[u][c]) at [c][u]
+            const cd b = cload(Bg, off_A(d, a, n, i) + (rc % NORB) * NORB + rc / NORB);
+            sAp[o] = TP(b.re);
+            sAp[o + 1] = TP(-b.im);
+        } else if constexpr (C::SPLIT_A) {
             sAp[o] = TP(v.re);
             sAp[o + 1] = TP(v.im);
         }
@@ -284,7 +294,7 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
         for (int t = 0; t < NORB; ++t) cfma(acc, cd{Ar[2 * t], Ar[2 * t + 1]}, gv[t]);
         if (!g_ok) acc = cd{0.0, 0.0};
         TP* X = sX + (g & 1) * C::XB + ((x_nl * EB + x_el) * 3 + x_i) * C::XR + 2 * x_u;
-        if constexpr (C::SPLIT_A)
+        if constexpr (PREC != SSE_FP64)  // the P tiles run on fp32 operands
             *reinterpret_cast<float2*>(X) = make_float2((float)acc.re, (float)acc.im);
         else
             *reinterpret_cast<double2*>(X) = make_double2(acc.re, acc.im);
@@ -586,32 +596,34 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     write_planes(nblk * EB - NW, NE);
 }
 
-template <int NORB, int NKZ, int NW, int NB, int EB, int PREC, int FLAGS>
-static hipError_t launch_fwd_flags(const Dims& d, const double* G, const double* D, const double* A,
+template <int NORB, int NKZ, int NW, int NB, int EB, int PREC, int FLAGS, bool HBA>
+static hipError_t launch_fwd_flags(const Dims& d, const double* G, const double* D, const double* A, const double* B,
                                    const int32_t* nbr, cd alpha, double* S, hipStream_t stream) {
-    using C = Fwd64<NORB, NKZ, NW, NB, EB, PREC>;
-    auto kern = fwd_mfma_kernel<NORB, NKZ, NW, NB, EB, PREC, FLAGS>;
+    using C = Fwd64<NORB, NKZ, NW, NB, EB, PREC, HBA>;
+    auto kern = fwd_mfma_kernel<NORB, NKZ, NW, NB, EB, PREC, FLAGS, HBA>;
     // set on every launch (cheap): the attribute is per device, and a process-wide
     // flag would race between host threads
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)C::LDS_BYTES);
     if (e != hipSuccess) return e;
     const int64_t groups = ((d.na + 7) / 8) * 8 * NORB;
-    hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(C::THREADS), C::LDS_BYTES, stream, d, G, D, A, nbr, alpha, S);
+    hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(C::THREADS), C::LDS_BYTES, stream, d, G, D, A, B, nbr, alpha,
+                       S);
     return hipGetLastError();
 }
 
 // the branch sets with a kernel instance: both (one pass), and the two passes
 // of the signed form (E - w terms written, E + w terms added)
-template <int NORB, int NKZ, int NW, int NB, int EB, int PREC>
-static hipError_t launch_fwd(const Dims& d, const double* G, const double* D, const double* A, const int32_t* nbr,
-                             cd alpha, double* S, hipStream_t stream, int flags) {
+template <int NORB, int NKZ, int NW, int NB, int EB, int PREC, bool HBA>
+static hipError_t launch_fwd(const Dims& d, const double* G, const double* D, const double* A, const double* B,
+                             const int32_t* nbr, cd alpha, double* S, hipStream_t stream, int flags) {
     constexpr int kBoth = kBranchMinus | kBranchPlus, kPlusAdd = kBranchPlus | kAccumulate;
-    if (flags == kBoth) return launch_fwd_flags<NORB, NKZ, NW, NB, EB, PREC, kBoth>(d, G, D, A, nbr, alpha, S, stream);
+    if (flags == kBoth)
+        return launch_fwd_flags<NORB, NKZ, NW, NB, EB, PREC, kBoth, HBA>(d, G, D, A, B, nbr, alpha, S, stream);
     if (flags == kBranchMinus)
-        return launch_fwd_flags<NORB, NKZ, NW, NB, EB, PREC, kBranchMinus>(d, G, D, A, nbr, alpha, S, stream);
+        return launch_fwd_flags<NORB, NKZ, NW, NB, EB, PREC, kBranchMinus, HBA>(d, G, D, A, B, nbr, alpha, S, stream);
     if (flags == kPlusAdd)
-        return launch_fwd_flags<NORB, NKZ, NW, NB, EB, PREC, kPlusAdd>(d, G, D, A, nbr, alpha, S, stream);
+        return launch_fwd_flags<NORB, NKZ, NW, NB, EB, PREC, kPlusAdd, HBA>(d, G, D, A, B, nbr, alpha, S, stream);
     return hipErrorInvalidValue;
 }
 
@@ -621,24 +633,34 @@ bool fwd_mfma_specialised(const Dims& d) {
            (d.norb == 10 && d.nkz == 7 && d.nw == 10 && d.nb == 3);
 }
 
+// energy blocks of 8 source energies; with a stored grad H_ba the fp64 form
+// takes blocks of 4, which leaves LDS room for the second right-factor table
+template <int NORB, int NKZ, int NW, int NB, int PREC>
+static hipError_t launch_shape(const Dims& d, const double* G, const double* D, const double* A, const double* B,
+                               const int32_t* nbr, cd alpha, double* S, hipStream_t stream, int flags) {
+    if (!B) return launch_fwd<NORB, NKZ, NW, NB, 8, PREC, false>(d, G, D, A, B, nbr, alpha, S, stream, flags);
+    return launch_fwd<NORB, NKZ, NW, NB, PREC == SSE_FP64 ? 4 : 8, PREC, true>(d, G, D, A, B, nbr, alpha, S, stream,
+                                                                                 flags);
+}
+
 template <int PREC>
-static hipError_t dispatch_fwd(const Dims& d, const double* G, const double* D, const double* A, const int32_t* nbr,
-                               cd alpha, double* S, hipStream_t stream, int flags) {
+static hipError_t dispatch_fwd(const Dims& d, const double* G, const double* D, const double* A, const double* B,
+                               const int32_t* nbr, cd alpha, double* S, hipStream_t stream, int flags) {
     if (d.norb == 10 && d.nkz == 7 && d.nw == 10 && d.nb == 4)
-        return launch_fwd<10, 7, 10, 4, 8, PREC>(d, G, D, A, nbr, alpha, S, stream, flags);
+        return launch_shape<10, 7, 10, 4, PREC>(d, G, D, A, B, nbr, alpha, S, stream, flags);
     if (d.norb == 10 && d.nkz == 7 && d.nw == 10 && d.nb == 3)
-        return launch_fwd<10, 7, 10, 3, 8, PREC>(d, G, D, A, nbr, alpha, S, stream, flags);
+        return launch_shape<10, 7, 10, 3, PREC>(d, G, D, A, B, nbr, alpha, S, stream, flags);
     if (d.norb == 4 && d.nkz == 3 && d.nw == 2 && d.nb == 4)
-        return launch_fwd<4, 3, 2, 4, 8, PREC>(d, G, D, A, nbr, alpha, S, stream, flags);
+        return launch_shape<4, 3, 2, 4, PREC>(d, G, D, A, B, nbr, alpha, S, stream, flags);
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_fwd_mfma(const Dims& d, int precision, const double* G, const double* D, const double* A,
-                           const int32_t* nbr, cd alpha, double* S, hipStream_t stream, int flags) {
-    if (precision == SSE_FP64) return dispatch_fwd<SSE_FP64>(d, G, D, A, nbr, alpha, S, stream, flags);
-    if (precision == SSE_FP32) return dispatch_fwd<SSE_FP32>(d, G, D, A, nbr, alpha, S, stream, flags);
+                           const double* B, const int32_t* nbr, cd alpha, double* S, hipStream_t stream, int flags) {
+    if (precision == SSE_FP64) return dispatch_fwd<SSE_FP64>(d, G, D, A, B, nbr, alpha, S, stream, flags);
+    if (precision == SSE_FP32) return dispatch_fwd<SSE_FP32>(d, G, D, A, B, nbr, alpha, S, stream, flags);
     if (precision == SSE_FP16X2 || precision == SSE_BF16X2)
-        return launch_fwd_h16(d, precision, G, D, A, nbr, alpha, S, stream, flags);
+        return launch_fwd_h16(d, precision, G, D, A, B, nbr, alpha, S, stream, flags);
     return hipErrorInvalidValue;
 }
 

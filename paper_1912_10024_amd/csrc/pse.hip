@@ -116,19 +116,23 @@ __device__ __forceinline__ void pse_sum_row_tile(const Dims& d, const double* re
     }
 }
 
-// ADJ = false: Pi (Eq. 4) with Gs, Go as documented above.
-// ADJ = true: the D part of the adjoint of Eq. 3 for dL/dSigma = g,
-//   dD[q, w-1, a, n][i][j] = conj(alpha) sum_{k', E'} sum_{s = +1, -1} [0 <= E' + s w < NE]
+// MODE = 0: Pi (Eq. 4) with Gs, Go as documented above.
+// MODE != 0: the D part of the adjoint of Eq. 3 for dL/dSigma = g,
+//   dD[q, w-1, a, n][i][j] = conj(alpha) sum_{k', E'} sum_{s in S} [0 <= E' + s w < NE]
 //                            sum_{r,c} conj((A_i G[k', E', b] A_j^H)[r][c]) g[k'+q, E'+s w, a][r][c],
-// which is the same contraction with Gs := g (no slot axis), both energy
-// branches summed into each A row, and T_ij = A_j . G^H . A_i^H (the Go block
-// is staged conjugate-transposed); beta = conj(alpha).
-template <int N, int NK, int NW, int NB, bool ADJ>
+// which is the same contraction with Gs := g (no slot axis), the energy
+// branches of S summed into each A row, and T_ij = A_j . G^H . A_i^H (the Go
+// block is staged conjugate-transposed); beta = conj(alpha).  MODE is the set
+// S: bit 0 the branch s = +1 (g at E' + w: the terms whose G sits at E - w,
+// i.e. the coefficients at +w), bit 1 the branch s = -1 (coefficients at -w);
+// the one-table form of Eq. 3 takes both.
+template <int N, int NK, int NW, int NB, int MODE>
 __global__ __launch_bounds__(64 * (8 + NB)) void pse_mfma_kernel(
     Dims d, const double* __restrict__ Gs, const double* __restrict__ Go, const double* __restrict__ Ag,
     const int32_t* __restrict__ nbr, cd beta, double* __restrict__ Pi) {
     using C = PseCfg<N, NK, NW, NB>;
     static_assert(C::THREADS == 64 * (8 + NB), "launch bounds");
+    constexpr bool ADJ = MODE != 0, UP = !ADJ || (MODE & 1) != 0, LO = ADJ && (MODE & 2) != 0;
     constexpr int NN = C::NN;
     extern __shared__ __align__(16) double smem[];
     double* sA = smem;           // [NB][3][N][N] complex
@@ -322,13 +326,20 @@ __global__ __launch_bounds__(64 * (8 + NB)) void pse_mfma_kernel(
                 const int kq = (k + r / NW) % NK;
                 const double* base = Gs + kq * rs_k + rs_slot * a;
                 ap[ml] = (ok ? base + (int64_t)es * rs_e : pse_zero_block) + 4 * kg + kk;
-                if constexpr (ADJ) {
+                if constexpr (LO) {
                     const bool ok2 = r < C::MROWS && E - w >= 0;
                     ap2[ml] = (ok2 ? base + (int64_t)(E - w) * rs_e : pse_zero_block) + 4 * kg + kk;
                 }
             }
         };
-        auto a_load = [&](int ml, int off) { return ADJ ? ap[ml][off] + ap2[ml][off] : ap[ml][off]; };
+        auto a_load = [&](int ml, int off) {
+            if constexpr (UP && LO)
+                return ap[ml][off] + ap2[ml][off];
+            else if constexpr (LO)
+                return ap2[ml][off];
+            else
+                return ap[ml][off];
+        };
         double an[C::ML];
         a_rows(0);
 #pragma unroll
@@ -467,11 +478,11 @@ bool pse_mfma_specialised(const Dims& d) {
     return d.norb == 10 && d.nkz == 7 && d.nqz == 7 && d.nw == 10 && (d.nb == 4 || d.nb == 3) && d.ne < (1 << 28);
 }
 
-template <int NB, bool ADJ>
+template <int NB, int MODE>
 static hipError_t launch_pse_mfma(const Dims& d, const double* Rs, const double* Go, const double* A,
                                   const int32_t* nbr, cd beta, double* out, hipStream_t stream) {
     using C = PseCfg<10, 7, 10, NB>;
-    auto kern = pse_mfma_kernel<10, 7, 10, NB, ADJ>;
+    auto kern = pse_mfma_kernel<10, 7, 10, NB, MODE>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)C::LDS_BYTES);
     if (e != hipSuccess) return e;
@@ -486,8 +497,8 @@ bool pse_generic_supported(const Dims& d) {
 hipError_t launch_pse(const Dims& d, const double* Gs, const double* Go, const double* A, const int32_t* nbr, cd beta,
                       double* Pi, hipStream_t stream) {
     if (pse_mfma_specialised(d))
-        return d.nb == 4 ? launch_pse_mfma<4, false>(d, Gs, Go, A, nbr, beta, Pi, stream)
-                         : launch_pse_mfma<3, false>(d, Gs, Go, A, nbr, beta, Pi, stream);
+        return d.nb == 4 ? launch_pse_mfma<4, 0>(d, Gs, Go, A, nbr, beta, Pi, stream)
+                         : launch_pse_mfma<3, 0>(d, Gs, Go, A, nbr, beta, Pi, stream);
     const size_t lds = pse_generic_lds(d);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(pse_generic_kernel),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -497,10 +508,19 @@ hipError_t launch_pse(const Dims& d, const double* Gs, const double* Go, const d
     return hipGetLastError();
 }
 
+template <int MODE>
+static hipError_t launch_dd_mode(const Dims& d, const double* G, const double* A, const int32_t* nbr, const double* gS,
+                                 cd calpha, double* dD, hipStream_t stream) {
+    return d.nb == 4 ? launch_pse_mfma<4, MODE>(d, gS, G, A, nbr, calpha, dD, stream)
+                     : launch_pse_mfma<3, MODE>(d, gS, G, A, nbr, calpha, dD, stream);
+}
+
 hipError_t launch_dd_mfma(const Dims& d, const double* G, const double* A, const int32_t* nbr, const double* gS,
-                          cd calpha, double* dD, hipStream_t stream) {
-    return d.nb == 4 ? launch_pse_mfma<4, true>(d, gS, G, A, nbr, calpha, dD, stream)
-                     : launch_pse_mfma<3, true>(d, gS, G, A, nbr, calpha, dD, stream);
+                          cd calpha, double* dD, hipStream_t stream, int branches) {
+    if (branches == 3) return launch_dd_mode<3>(d, G, A, nbr, gS, calpha, dD, stream);
+    if (branches == 1) return launch_dd_mode<1>(d, G, A, nbr, gS, calpha, dD, stream);
+    if (branches == 2) return launch_dd_mode<2>(d, G, A, nbr, gS, calpha, dD, stream);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace sse

@@ -13,30 +13,36 @@ constexpr int kAccumulate = 4;   // Sigma += result instead of Sigma = result
 
 // direct term-by-term fp64 forward (any shape with norb^2 <= 1024); the terms
 // with G at E - w read Dp, those with G at E + w read Dm (Dm == Dp: the
-// one-table form of sse_forward)
+// one-table form of sse_forward); B = stored grad_j H_ba blocks (layout of A),
+// or nullptr for A^H
 bool generic_supported(const Dims& d);
 hipError_t launch_fwd_generic(const Dims& d, const double* G, const double* Dp, const double* Dm, const double* A,
-                              const int32_t* nbr, cd alpha, double* S, hipStream_t stream);
+                              const double* B, const int32_t* nbr, cd alpha, double* S, hipStream_t stream);
 
 // matrix-core forward (fp64 or fp32 operands; the split 16-bit forms go to
 // launch_fwd_h16) for the shapes it is
 // instantiated for; flags selects the energy branches (kBranchMinus,
 // kBranchPlus) and whether the result is added to Sigma (kAccumulate)
+// B: stored grad_j H_ba blocks (layout of A) as the right factor, or nullptr for A^H
 bool fwd_mfma_specialised(const Dims& d);
 hipError_t launch_fwd_mfma(const Dims& d, int precision, const double* G, const double* D, const double* A,
-                           const int32_t* nbr, cd alpha, double* S, hipStream_t stream,
+                           const double* B, const int32_t* nbr, cd alpha, double* S, hipStream_t stream,
                            int flags = kBranchMinus | kBranchPlus);
 
 // matrix-core forward with split 16-bit operands (SSE_FP16X2, SSE_BF16X2) for
-// the shapes of fwd_mfma_specialised; flags as for launch_fwd_mfma
+// the shapes of fwd_mfma_specialised; B and flags as for launch_fwd_mfma
 hipError_t launch_fwd_h16(const Dims& d, int precision, const double* G, const double* D, const double* A,
-                          const int32_t* nbr, cd alpha, double* S, hipStream_t stream, int flags);
+                          const double* B, const int32_t* nbr, cd alpha, double* S, hipStream_t stream, int flags);
 
-// adjoint (fp64): reverse adjacency in the workspace, then dG/d gradH per neighbour atom and dD per edge
+// adjoint (fp64): reverse adjacency in the workspace, then dG/d gradH per neighbour atom and dD per edge.
+// signed_form: the terms with G at E - w read Dp and feed dDp, those at E + w
+// read Dm and feed dDm; otherwise Dp is the one table and dDp its gradient (Dm,
+// dDm unused).
 size_t bwd_workspace_bytes(const Dims& d);
 bool bwd_supported(const Dims& d);
-hipError_t launch_bwd(const Dims& d, const double* G, const double* D, const double* A, const int32_t* nbr, cd alpha,
-                      const double* gS, double* dG, double* dD, double* dA, void* ws, hipStream_t stream);
+hipError_t launch_bwd(const Dims& d, const double* G, const double* Dp, const double* Dm, const double* A,
+                      const int32_t* nbr, cd alpha, const double* gS, double* dG, double* dDp, double* dDm, double* dA,
+                      void* ws, hipStream_t stream, bool signed_form);
 
 // Eq. 3 bracket from the full phonon blocks (symmetric neighbour table)
 size_t combine_workspace_bytes(const Dims& d);
@@ -50,9 +56,11 @@ bool pse_mfma_specialised(const Dims& d);
 bool pse_generic_supported(const Dims& d);
 hipError_t launch_pse(const Dims& d, const double* Gs, const double* Go, const double* A, const int32_t* nbr, cd beta,
                       double* Pi, hipStream_t stream);
-// the D gradient of the adjoint on the same matrix-core kernel (shapes with pse_mfma_specialised)
+// the D gradient of the adjoint on the same matrix-core kernel (shapes with
+// pse_mfma_specialised); branches: 1 the terms with G at E - w (coefficients at
+// +w), 2 those with G at E + w (at -w), 3 both (the one-table form)
 hipError_t launch_dd_mfma(const Dims& d, const double* G, const double* A, const int32_t* nbr, const double* gS,
-                          cd calpha, double* dD, hipStream_t stream);
+                          cd calpha, double* dD, hipStream_t stream, int branches = 3);
 
 // neighbour-table range check: sets *flag (device int) to 1 if any entry is outside [0, na)
 hipError_t launch_check_nbr(const Dims& d, const int32_t* nbr, int* flag, hipStream_t stream);

@@ -113,23 +113,37 @@ def combine_d(Dfull: torch.Tensor, nbr: torch.Tensor) -> torch.Tensor:
 
 def forward(G, D, dH, nbr, alpha=1j, precision: str = "fp64", out=None, ws=None) -> torch.Tensor:
     """Sigma[nkz, ne, na, norb, norb] = Eq. 3 (one of lesser/greater)."""
-    return _forward(G, D, D, dH, nbr, alpha, precision, out, ws)
+    return _forward(G, D, D, dH, None, nbr, alpha, precision, out, ws)
 
 
 def forward_signed(G, Dp, Dm, dH, nbr, alpha=1j, precision: str = "fp64", out=None, ws=None) -> torch.Tensor:
     """Sigma of Eq. 3 over both signs of the frequency: the terms with G at
     E - w read Dp (coefficients at +w), those with G at E + w read Dm (at -w);
     both in D's layout.  Dm is Dp gives forward()."""
-    if Dm is Dp:
-        return _forward(G, Dp, Dp, dH, nbr, alpha, precision, out, ws)
-    Dp, Dm = _resolved(Dp), _resolved(Dm)
-    _check_tensor(Dm, "Dm")
-    if Dm.shape != Dp.shape:
-        raise ValueError(f"Dm must have Dp's shape {tuple(Dp.shape)}")
-    return _forward(G, Dp, Dm, dH, nbr, alpha, precision, out, ws)
+    return forward_ex(G, Dp, dH, nbr, Dm=Dm, alpha=alpha, precision=precision, out=out, ws=ws)
 
 
-def _forward(G, D, Dm, dH, nbr, alpha, precision, out, ws) -> torch.Tensor:
+def forward_ex(G, Dp, dH, nbr, Dm=None, dHba=None, alpha=1j, precision: str = "fp64", out=None, ws=None) -> torch.Tensor:
+    """Sigma of Eq. 3 with its full input contract: Dm (coefficients at -w, for
+    the terms with G at E + w; None or Dp itself: the one-table form) and dHba,
+    the stored right factor grad_j H_ba[a, n, j] in dH's layout (None: the
+    Hermitian reading dH^H)."""
+    if Dm is None or Dm is Dp:
+        Dm = Dp
+    else:
+        Dp, Dm = _resolved(Dp), _resolved(Dm)
+        _check_tensor(Dm, "Dm")
+        if Dm.shape != Dp.shape:
+            raise ValueError(f"Dm must have Dp's shape {tuple(Dp.shape)}")
+    if dHba is not None:
+        dHba = _resolved(dHba)
+        _check_tensor(dHba, "dHba")
+        if dHba.shape != dH.shape:
+            raise ValueError(f"dHba must have dH's shape {tuple(dH.shape)}")
+    return _forward(G, Dp, Dm, dH, dHba, nbr, alpha, precision, out, ws)
+
+
+def _forward(G, D, Dm, dH, dHba, nbr, alpha, precision, out, ws) -> torch.Tensor:
     same = Dm is D
     G, D, dH = _resolved(G), _resolved(D), _resolved(dH)
     Dm = D if same else Dm
@@ -150,7 +164,11 @@ def _forward(G, D, Dm, dH, nbr, alpha, precision, out, ws) -> torch.Tensor:
     lib = _lib.load()
     cd = _lib.SSEDims.of(d)
     a = complex(alpha)
-    if Dm is D or Dm.data_ptr() == D.data_ptr():
+    if dHba is not None:
+        rc = lib.sse_forward_ex(ctypes.byref(cd), _ptr(G), _ptr(D), _ptr(Dm), _ptr(dH), _ptr(dHba), _ptr(nbr), a.real,
+                                a.imag, PRECISIONS[precision], _ptr(out), _ptr(ws), ws.numel(), _stream(G.device))
+        _raise(rc, "sse_forward_ex")
+    elif Dm is D or Dm.data_ptr() == D.data_ptr():
         rc = lib.sse_forward(ctypes.byref(cd), _ptr(G), _ptr(D), _ptr(dH), _ptr(nbr), a.real, a.imag,
                              PRECISIONS[precision], _ptr(out), _ptr(ws), ws.numel(), _stream(G.device))
         _raise(rc, "sse_forward")
@@ -218,6 +236,32 @@ def backward(G, D, dH, nbr, dSigma, alpha=1j, need=(True, True, True), ws=None):
     return dG, dD, ddH
 
 
+def backward_signed(G, Dp, Dm, dH, nbr, dSigma, alpha=1j, need=(True, True, True, True), ws=None):
+    """(dL/dG, dL/dDp, dL/dDm, dL/d dH) through forward_signed, for dSigma = dL/dSigma."""
+    G, Dp, Dm, dH, dSigma = (_resolved(t) for t in (G, Dp, Dm, dH, dSigma))
+    d = dims_of(G, Dp, dH, nbr)
+    for t, n in ((G, "G"), (Dp, "Dp"), (Dm, "Dm"), (dH, "dH"), (dSigma, "dSigma")):
+        _check_tensor(t, n)
+    _check_tensor(nbr, "nbr", torch.int32)
+    if tuple(Dm.shape) != d.d_shape or tuple(dSigma.shape) != d.sigma_shape:
+        raise ValueError(f"Dm must be {d.d_shape} and dSigma {d.sigma_shape}")
+    dev = G.device
+    dG = torch.empty(d.g_shape, dtype=torch.complex128, device=dev) if need[0] else None
+    dDp = torch.empty(d.d_shape, dtype=torch.complex128, device=dev) if need[1] else None
+    dDm = torch.empty(d.d_shape, dtype=torch.complex128, device=dev) if need[2] else None
+    ddH = torch.empty(d.dh_shape, dtype=torch.complex128, device=dev) if need[3] else None
+    if ws is None:
+        ws = workspace(d, backward=True, device=dev)
+    lib = _lib.load()
+    cd = _lib.SSEDims.of(d)
+    a = complex(alpha)
+    rc = lib.sse_backward_signed(ctypes.byref(cd), _ptr(G), _ptr(Dp), _ptr(Dm), _ptr(dH), _ptr(nbr), a.real, a.imag,
+                                 _ptr(dSigma), _ptr(dG), _ptr(dDp), _ptr(dDm), _ptr(ddH), _ptr(ws), ws.numel(),
+                                 _stream(dev))
+    _raise(rc, "sse_backward_signed")
+    return dG, dDp, dDm, ddH
+
+
 class SSEFunction(torch.autograd.Function):
     """Sigma = SSE(G, D, dH) with the hand-written adjoint as backward.
 
@@ -241,3 +285,27 @@ class SSEFunction(torch.autograd.Function):
 def sse(G, D, dH, nbr, alpha=1j):
     """Differentiable Sigma (autograd through the hand-written adjoint)."""
     return SSEFunction.apply(G, D, dH, nbr, alpha)
+
+
+class SSESignedFunction(torch.autograd.Function):
+    """Sigma = SSE over signed frequencies (Dp at +w, Dm at -w) with the
+    hand-written adjoint as backward; saves only the inputs."""
+
+    @staticmethod
+    def forward(ctx, G, Dp, Dm, dH, nbr, alpha=1j):
+        ctx.save_for_backward(G, Dp, Dm, dH, nbr)
+        ctx.alpha = complex(alpha)
+        return forward_ex(G, Dp, dH, nbr, Dm=Dm, alpha=alpha)
+
+    @staticmethod
+    def backward(ctx, gS):
+        G, Dp, Dm, dH, nbr = ctx.saved_tensors
+        need = ctx.needs_input_grad[:4]
+        dG, dDp, dDm, ddH = backward_signed(G, Dp, Dm, dH, nbr, _resolved(gS).contiguous(), alpha=ctx.alpha,
+                                            need=need)
+        return dG, dDp, dDm, ddH, None, None
+
+
+def sse_signed(G, Dp, Dm, dH, nbr, alpha=1j):
+    """Differentiable Sigma over signed frequencies (autograd through the hand-written adjoint)."""
+    return SSESignedFunction.apply(G, Dp, Dm, dH, nbr, alpha)
