@@ -223,6 +223,28 @@ int sse_backward_signed(const sse_dims* dims, const double* G, const double* Dp,
                         void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * sse_backward for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results, with the workspace in a device array that is part
+ * of the library (sse_noalloc_scratch_bytes() bytes, 64 MiB, held by every GPU
+ * the library runs on until the process ends) instead of a caller-provided
+ * buffer.  Calls no hipMalloc, hipFree or allocating routine.  Dims whose
+ * sse_backward workspace exceeds the array are rejected with
+ * SSE_ERR_WORKSPACE before anything is launched (at Nkz = 7, Norb = 10, Nb = 4
+ * the d(dH) shares take 16 * Nkz * Na * Nb * 3 * Norb^2 bytes: about 4,900
+ * atoms with ddH, far more without it).  Every call on one GPU uses that GPU's
+ * array (the current device's): calls that overlap on one GPU race.  The
+ * kernels rewrite every part of the array they read, so no clearing is needed
+ * between calls.  Other arguments and errors as for sse_backward.
+ */
+int sse_backward_noalloc(const sse_dims* dims, const double* G, const double* D, const double* dH,
+                         const int32_t* nbr, double alpha_re, double alpha_im, const double* dSigma,
+                         double* dG, double* dD, double* ddH, void* stream);
+
+/* Size in bytes of the device array behind sse_backward_noalloc. */
+size_t sse_noalloc_scratch_bytes(void);
+
+/*
  * The bracket of Eq. 3 for every neighbour slot, the step that prepares D:
  *   D[q,w,a,n,:,:] = Dfull[q,w,b,1+m] - Dfull[q,w,b,0] - Dfull[q,w,a,0] + Dfull[q,w,a,1+n]
  * (= D_ba - D_bb - D_aa + D_ab) with b = nbr[a,n] and m the slot with

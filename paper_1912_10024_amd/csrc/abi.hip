@@ -24,6 +24,20 @@ int ok() {
     return SSE_OK;
 }
 
+}  // namespace
+
+namespace sse {
+int set_error(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+}  // namespace sse
+
+namespace {
+
 // a*b with overflow detection for non-negative operands
 bool mul_ok(int64_t a, int64_t b, int64_t* out) {
     if (a < 0 || b < 0) return false;

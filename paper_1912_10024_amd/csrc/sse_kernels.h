@@ -62,6 +62,9 @@ hipError_t launch_pse(const Dims& d, const double* Gs, const double* Go, const d
 hipError_t launch_dd_mfma(const Dims& d, const double* G, const double* A, const int32_t* nbr, const double* gS,
                           cd calpha, double* dD, hipStream_t stream, int branches = 3);
 
+// sets the thread-local text that sse_last_error returns; returns code
+int set_error(int code, const char* fmt, ...);
+
 // neighbour-table range check: sets *flag (device int) to 1 if any entry is outside [0, na)
 hipError_t launch_check_nbr(const Dims& d, const int32_t* nbr, int* flag, hipStream_t stream);
 

@@ -236,6 +236,32 @@ def backward(G, D, dH, nbr, dSigma, alpha=1j, need=(True, True, True), ws=None):
     return dG, dD, ddH
 
 
+def backward_noalloc(G, D, dH, nbr, dSigma, alpha=1j, dG=None, dD=None, ddH=None):
+    """sse_backward_noalloc: the adjoint into caller-provided outputs (any may be
+    None to skip that gradient) with no device allocation in the library; the
+    workspace is the library's own device array (at most
+    sse_noalloc_scratch_bytes() bytes of workspace)."""
+    G, D, dH, dSigma = _resolved(G), _resolved(D), _resolved(dH), _resolved(dSigma)
+    d = dims_of(G, D, dH, nbr)
+    for t, n in ((G, "G"), (D, "D"), (dH, "dH"), (dSigma, "dSigma")):
+        _check_tensor(t, n)
+    _check_tensor(nbr, "nbr", torch.int32)
+    for t, n, shape in ((dG, "dG", d.g_shape), (dD, "dD", d.d_shape), (ddH, "ddH", d.dh_shape)):
+        if t is not None:
+            _check_tensor(t, n)
+            if tuple(t.shape) != shape:
+                raise ValueError(f"{n} must be {shape}")
+    if tuple(dSigma.shape) != d.sigma_shape:
+        raise ValueError(f"dSigma must be {d.sigma_shape}")
+    lib = _lib.load()
+    cd = _lib.SSEDims.of(d)
+    a = complex(alpha)
+    rc = lib.sse_backward_noalloc(ctypes.byref(cd), _ptr(G), _ptr(D), _ptr(dH), _ptr(nbr), a.real, a.imag,
+                                  _ptr(dSigma), _ptr(dG), _ptr(dD), _ptr(ddH), _stream(G.device))
+    _raise(rc, "sse_backward_noalloc")
+    return dG, dD, ddH
+
+
 def backward_signed(G, Dp, Dm, dH, nbr, dSigma, alpha=1j, need=(True, True, True, True), ws=None):
     """(dL/dG, dL/dDp, dL/dDm, dL/d dH) through forward_signed, for dSigma = dL/dSigma."""
     G, Dp, Dm, dH, dSigma = (_resolved(t) for t in (G, Dp, Dm, dH, dSigma))

@@ -1,0 +1,58 @@
+"""sse_backward_noalloc (the adjoint with the library's own device array as its
+workspace) against sse_backward with a caller-provided workspace: the same
+kernels, so the gradients agree bit for bit, on two calls in a row, the second
+with a smaller input; a size beyond the array is refused before any launch."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1912_10024_amd import _lib, sse
+from paper_1912_10024_amd.inputs import Dims, anti_hermitian_blocks, make_nbr
+
+pytestmark = pytest.mark.gpu
+
+
+def _rand(d: Dims, seed: int):
+    rng = np.random.default_rng(seed)
+
+    def cn(shape, s=1.0):
+        return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) * s
+
+    inp = dict(G=anti_hermitian_blocks(cn(d.g_shape)), D=cn(d.d_shape), dH=cn(d.dh_shape, 0.1),
+               nbr=make_nbr(rng, d.na, d.nb), W=cn(d.sigma_shape))
+    return {k: torch.from_numpy(v).cuda() for k, v in inp.items()}
+
+
+def test_noalloc_backward_matches_workspace_backward_twice():
+    big = Dims(nkz=7, ne=20, nqz=7, nw=10, na=12, nb=4, norb=10, g_slots=2)   # matrix-core dD kernel
+    small = Dims(nkz=3, ne=16, nqz=3, nw=2, na=16, nb=4, norb=4, g_slots=1)   # a different, smaller problem
+    for d, seed in ((big, 1), (small, 2)):
+        print(f"[gpu] backward_noalloc dims={d.as_tuple()}", flush=True)
+        t = _rand(d, seed)
+        gS = t["W"].conj().transpose(-1, -2).contiguous()
+        ref = sse.backward(t["G"], t["D"], t["dH"], t["nbr"], gS, alpha=0.3 + 0.7j)
+        out = (torch.full(d.g_shape, complex(float("nan"), float("nan")), dtype=torch.complex128, device="cuda"),
+               torch.full(d.d_shape, complex(float("nan"), float("nan")), dtype=torch.complex128, device="cuda"),
+               torch.full(d.dh_shape, complex(float("nan"), float("nan")), dtype=torch.complex128, device="cuda"))
+        got = sse.backward_noalloc(t["G"], t["D"], t["dH"], t["nbr"], gS, alpha=0.3 + 0.7j, dG=out[0], dD=out[1],
+                                   ddH=out[2])
+        torch.cuda.synchronize()
+        for name, g, r in zip(("dG", "dD", "ddH"), got, ref):
+            assert torch.equal(g, r), f"{name} differs at dims {d.as_tuple()}"
+
+
+def test_noalloc_refuses_a_workspace_beyond_its_array():
+    lib = _lib.load()
+    cap = int(lib.sse_noalloc_scratch_bytes())
+    d = Dims(nkz=7, ne=4, nqz=7, nw=10, na=20000, nb=4, norb=10, g_slots=1)
+    need = ctypes.c_size_t(0)
+    assert lib.sse_workspace_bytes(ctypes.byref(_lib.SSEDims.of(d)), 0, 1, ctypes.byref(need)) == _lib.SSE_OK
+    assert need.value > cap
+    # NULL tensors: the size check comes first (and NULL pointers would be refused
+    # before any launch anyway)
+    rc = lib.sse_backward_noalloc(ctypes.byref(_lib.SSEDims.of(d)), None, None, None, None, 0.0, 1.0, None,
+                                  None, None, None, None)
+    assert rc == _lib.SSE_ERR_WORKSPACE
+    assert "above its" in _lib.last_error()
