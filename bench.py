@@ -152,18 +152,30 @@ def phonon_sample_error(d, Gs, Go, dH, nbr, P, seed=11):
     return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
 
 
-def recorded_traffic(record="fwd_mfma_device_traffic.txt", source="fwd_mfma.hip"):
-    """HBM bytes per launch of a kernel from the committed rocprofv3 counters,
-    if the kernel source is unchanged since they were taken."""
+def kernel_source_hash(sources) -> str:
+    """sha256 over the files a kernel is compiled from (in the given order)."""
     import hashlib
 
+    h = hashlib.sha256()
+    for f in sources:
+        with open(os.path.join(ROOT, "paper_1912_10024_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+FWD_SOURCES = ("fwd_mfma.hip", "fwd_common.h", "sse_common.h")
+H16_SOURCES = ("fwd_h16.hip", "fwd_common.h", "sse_common.h")
+PSE_SOURCES = ("pse.hip", "sse_common.h")
+
+
+def recorded_traffic(record, sources):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counters,
+    if the kernel's sources are unchanged since they were taken."""
     rec = os.path.join(ROOT, "profiles", record)
-    src = os.path.join(ROOT, "paper_1912_10024_amd", "csrc", source)
     if not os.path.exists(rec):
         return None
     kv = dict(l.strip().split("=", 1) for l in open(rec) if "=" in l and not l.startswith("#"))
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if kv.get("kernel_source_sha256") != sha:
+    if kv.get("kernel_source_sha256") != kernel_source_hash(sources):
         return None
     return float(kv["fetch_bytes"]) + float(kv["write_bytes"])
 
@@ -225,7 +237,7 @@ def phonon_record(args, sse, flops, d, G, dH, nbr, dev):
         "roofline": {"bound": "mfma", "achieved": round(useful / (ms * 1e-3) / 1e12, 3),
                      "peak": FP64_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
                      "frac": round(useful / (ms * 1e-3) / FP64_MFMA_PEAK, 4),
-                     "traffic": (recorded_traffic("pse_mfma_device_traffic.txt", "pse.hip")
+                     "traffic": (recorded_traffic("pse_mfma_device_traffic.txt", PSE_SOURCES)
                                  if args.config == "device" else None),
                      "flops_per_launch": useful,
                      "what": "useful fp64 flops: the trace contraction on the matrix cores plus T = gradH.Go.gradH^H "
@@ -331,10 +343,20 @@ def main():
     if not args.no_cpu:
         f_block = f_eff / (d.nkz * d.ne * d.na)
         cpu, cpu_pts, cpu_ref = cpu_baseline(d, G, D, dH, nbr, args.cpu_seconds, f_block)
-    gemm = flops.pd_mfma_flops(d)
     peaks = {"fp64": FP64_MFMA_PEAK, "fp32": FP32_MFMA_PEAK, "bf16x2": FP16_MFMA_PEAK, "fp16x2": FP16_MFMA_PEAK}
-    # 16-bit hi/lo forms: the four partial products of the P.D GEMM on the 16-bit matrix cores
-    mfma_flops = {"fp64": gemm, "fp32": gemm, "bf16x2": 4 * flops.pd_gemm_flops(d), "fp16x2": 4 * flops.pd_gemm_flops(d)}
+    # fp64: the useful flops of the regrouped form (GEMM and all twelve products
+    # that form P; vector ALUs and matrix cores share the fp64 peak); fp32: the
+    # fp32 matrix-core work (GEMM and the nine right products); 16-bit forms: the
+    # four hi/lo partial products of both on the 16-bit matrix cores
+    mfma_flops = {"fp64": flops.pd_useful_flops(d), "fp32": flops.pd_mfma_flops(d),
+                  "bf16x2": flops.split16_mfma_flops(d), "fp16x2": flops.split16_mfma_flops(d)}
+    whats = {"fp64": "useful fp64 flops: P.D GEMM + the 12 products forming P (X on the vector ALUs, X.gradH^H on "
+                     "the matrix cores; one shared fp64 peak)",
+             "fp32": "fp32 matrix-core flops: P.D GEMM + P = X.gradH^H products",
+             "bf16x2": "16-bit matrix-core flops: 4 hi/lo products of the P.D GEMM and of P = X.gradH^H",
+             "fp16x2": "16-bit matrix-core flops: 4 hi/lo products of the P.D GEMM and of P = X.gradH^H"}
+    traffic_records = {"fp64": ("fwd_mfma_device_traffic.txt", FWD_SOURCES),
+                       "fp16x2": ("fwd_h16_device_traffic.txt", H16_SOURCES)}
     res = {}
     for form in forms:
         S = torch.empty(d.sigma_shape, dtype=torch.complex128, device=dev)
@@ -348,19 +370,16 @@ def main():
             "kernel_ms": ms,
             "kernel_ms_all": [round(x, 3) for x in kern_ms],
             "roofline": {"bound": "mfma", "achieved": round(achieved / 1e12, 3), "peak": peaks[form] / 1e12,
-                         "unit": "TFLOP/s", "frac": round(achieved / peaks[form], 4), "traffic": None,
-                         "flops_per_launch": mfma_flops[form],
-                         "what": (f"useful {form} matrix-core flops: P.D GEMM + P = X.gradH^H products"
-                                  if form in ("fp64", "fp32") else
-                                  "16-bit matrix-core flops of the P.D GEMM (4 hi/lo products)")},
+                         "unit": "TFLOP/s", "frac": round(achieved / peaks[form], 4),
+                         "traffic": (recorded_traffic(*traffic_records[form])
+                                     if form in traffic_records and args.config == "device" else None),
+                         "flops_per_launch": mfma_flops[form], "what": whats[form]},
         }
         if cpu is not None:
             res[form]["err"] = sampled_error(S, cpu_pts, cpu_ref)
         del S, ws
         torch.cuda.empty_cache()
     head = forms[0]
-    if head == "fp64" and args.config == "device":
-        res[head]["roofline"]["traffic"] = recorded_traffic()
     line = {
         "metric": "SSE effective TFLOP/s (paper's regrouped flop count, one Sigma component), fp64 vs mixed",
         "value": round(res[head]["value"], 3),

@@ -52,6 +52,21 @@ def pd_mfma_flops(d) -> float:
     return pd_gemm_flops(d) + 8.0 * d.norb ** 3 * 9 * d.nb * d.na * d.nkz * d.ne
 
 
+def pd_useful_flops(d) -> float:
+    """The regrouped form's useful flops: the P.D GEMM plus the twelve Norb^3
+    products per (k', E', a, n) that form P (X = grad_i H . G on the vector ALUs,
+    P = X . grad_j H^H on the matrix cores); on MI355X the fp64 vector ALUs and
+    matrix cores share the 78.6 TFLOP/s peak."""
+    return pd_gemm_flops(d) + pd_left_flops(d)
+
+
+def split16_mfma_flops(d) -> float:
+    """Flops the split 16-bit forms issue on the 16-bit matrix cores: the four
+    hi/lo partial products of the P.D GEMM and of the nine right products P =
+    X . grad_j H^H (the X rows stay on the fp64 vector ALUs)."""
+    return 4.0 * pd_mfma_flops(d)
+
+
 def pd_stencil_flops(d) -> float:
     """Real adds of the (w, +/-) energy stencil: 2 complex adds per valid (k, E, w, s, r, c)."""
     valid = 0
