@@ -19,6 +19,8 @@
 // edge order), so every output element has one owner: no atomics, bitwise
 // reproducible.  dD is formed by one workgroup per edge here, or by the
 // matrix-core phonon kernel in its adjoint mode for the shape it covers.
+#include <algorithm>
+
 #include "sse_kernels.h"
 
 namespace sse {
@@ -98,8 +100,17 @@ __global__ void zero_i32_kernel(int64_t n, int32_t* p) {
 static size_t bwd_csr_bytes(const Dims& d) {
     return (sizeof(int32_t) * (size_t)(3 * d.na + 1 + d.na * d.nb) + 255) / 256 * 256;
 }
+// the matrix-core kernel keeps one d gradH share per range of energies instead
+static bool bwd_use_mfma(const Dims& d, bool signed_form) {
+    return !signed_form && bwd_mfma_specialised(d) && d.ne < (int64_t(1) << 28) &&
+           d.na * bwd_mfma_shares(d) <= INT32_MAX;
+}
+static int64_t bwd_shares(const Dims& d, bool signed_form) {
+    return bwd_use_mfma(d, signed_form) ? bwd_mfma_shares(d) : d.nkz;
+}
 size_t bwd_workspace_bytes(const Dims& d) {
-    return bwd_csr_bytes(d) + sizeof(cd) * (size_t)(d.nkz * d.na * d.nb * 3 * d.norb * d.norb);
+    const int64_t shares = std::max(bwd_shares(d, false), bwd_shares(d, true));
+    return bwd_csr_bytes(d) + sizeof(cd) * (size_t)(shares * d.na * d.nb * 3 * d.norb * d.norb);
 }
 
 // --------------------------------------------------------------- W and Y of one source point
@@ -291,16 +302,17 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_dg_dh_kernel(Dims d, const do
     }
 }
 
-// d gradH of every edge (a, n): its Nkz per-k' sums added in k' order; an edge
-// whose neighbour entry lies outside [0, na) has no terms and gets zero
+// d gradH of every edge (a, n): its partial sums (one per momentum k', or per
+// energy range on the matrix-core path) added in share order; an edge whose
+// neighbour entry lies outside [0, na) has no terms and gets zero
 __global__ void bwd_dh_reduce_kernel(Dims d, const int32_t* __restrict__ nbr, const double* __restrict__ dApart,
-                                     double* __restrict__ dA) {
+                                     int64_t shares, double* __restrict__ dA) {
     const int64_t NN3 = 3 * d.norb * d.norb, per_k = d.na * d.nb * NN3;
     for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < per_k; x += (int64_t)gridDim.x * blockDim.x) {
         const int32_t b = nbr[x / NN3];
         cd s{0.0, 0.0};
         if (b >= 0 && b < d.na)
-            for (int64_t kp = 0; kp < d.nkz; ++kp) {
+            for (int64_t kp = 0; kp < shares; ++kp) {
                 const cd v = cload(dApart, kp * per_k + x);
                 s.re += v.re;
                 s.im += v.im;
@@ -425,12 +437,14 @@ hipError_t launch_bwd(const Dims& d, const double* G, const double* Dp, const do
                       const int32_t* nbr, cd alpha, const double* gS, double* dG, double* dDp, double* dDm, double* dA,
                       void* ws, hipStream_t stream, bool signed_form) {
     const cd calpha{alpha.re, -alpha.im};
+    const bool mfma = bwd_use_mfma(d, signed_form);
     // every attribute is set before the first launch, so a failure leaves all outputs untouched
     const size_t lds = bwd_lds_dg(d, signed_form);
     auto kern = signed_form ? bwd_dg_dh_kernel<true> : bwd_dg_dh_kernel<false>;
     if (dG || dA) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipError_t e = mfma ? bwd_mfma_prepare()
+                            : hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     if ((dDp || dDm) && !pse_mfma_specialised(d)) {
@@ -451,15 +465,21 @@ hipError_t launch_bwd(const Dims& d, const double* G, const double* Dp, const do
         const unsigned g2 = (unsigned)((d.na + 255) / 256 < 4096 ? (d.na + 255) / 256 : 4096);
         hipLaunchKernelGGL(rcsr_sort_kernel, dim3(g2), dim3(256), 0, stream, d.na, offset, edges);
         double* dApart = dA ? reinterpret_cast<double*>(reinterpret_cast<char*>(ws) + bwd_csr_bytes(d)) : nullptr;
-        const int64_t groups = (d.na + 7) / 8 * 8 * d.nkz;
-        hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(kBwdThreads), lds, stream, d, G, Dp, Dm, A, gS, calpha,
-                           offset, edges, dG, dApart);
-        hipError_t e = hipGetLastError();
+        hipError_t e;
+        if (mfma) {
+            e = launch_bwd_mfma(d, G, Dp, A, gS, calpha, offset, edges, dG, dApart, stream);
+        } else {
+            const int64_t groups = (d.na + 7) / 8 * 8 * d.nkz;
+            hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(kBwdThreads), lds, stream, d, G, Dp, Dm, A, gS,
+                               calpha, offset, edges, dG, dApart);
+            e = hipGetLastError();
+        }
         if (e != hipSuccess) return e;
         if (dA) {
             const int64_t n = d.na * d.nb * 3 * d.norb * d.norb;
             const unsigned g3 = (unsigned)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
-            hipLaunchKernelGGL(bwd_dh_reduce_kernel, dim3(g3), dim3(256), 0, stream, d, nbr, dApart, dA);
+            hipLaunchKernelGGL(bwd_dh_reduce_kernel, dim3(g3), dim3(256), 0, stream, d, nbr, dApart,
+                               bwd_shares(d, signed_form), dA);
             e = hipGetLastError();
             if (e != hipSuccess) return e;
         }

@@ -34,12 +34,21 @@ hipError_t launch_fwd_mfma(const Dims& d, int precision, const double* G, const 
 hipError_t launch_fwd_h16(const Dims& d, int precision, const double* G, const double* D, const double* A,
                           const double* B, const int32_t* nbr, cd alpha, double* S, hipStream_t stream, int flags);
 
-// adjoint (fp64): reverse adjacency in the workspace, then dG/d gradH per neighbour atom and dD per edge.
+// adjoint (fp64): reverse adjacency in the workspace, then dG/d gradH per neighbour atom and dD.
 // signed_form: the terms with G at E - w read Dp and feed dDp, those at E + w
 // read Dm and feed dDm; otherwise Dp is the one table and dDp its gradient (Dm,
 // dDm unused).
 size_t bwd_workspace_bytes(const Dims& d);
 bool bwd_supported(const Dims& d);
+// dG and d gradH of the one-table form on the matrix cores (Norb = 10, Nkz = Nqz = 7,
+// Nw = 10): one workgroup per (neighbour atom, range of energies), one d gradH
+// share per range (bwd_mfma_shares of them) in dApart
+bool bwd_mfma_specialised(const Dims& d);
+int64_t bwd_mfma_shares(const Dims& d);
+hipError_t bwd_mfma_prepare();
+hipError_t launch_bwd_mfma(const Dims& d, const double* G, const double* D, const double* A, const double* gS, cd calpha,
+                           const int32_t* offset, const int32_t* edges, double* dG, double* dApart,
+                           hipStream_t stream);
 hipError_t launch_bwd(const Dims& d, const double* G, const double* Dp, const double* Dm, const double* A,
                       const int32_t* nbr, cd alpha, const double* gS, double* dG, double* dDp, double* dDm, double* dA,
                       void* ws, hipStream_t stream, bool signed_form);

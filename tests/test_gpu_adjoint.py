@@ -57,6 +57,27 @@ def test_backward_matches_oracle(dims, seed):
     assert torch.count_nonzero(dG[:, :, :, 1:]) == 0
 
 
+def test_backward_energy_ranges_and_unreached_atom():
+    """Three ranges of energies (the matrix-core adjoint takes 32 per workgroup,
+    the last one ragged), and an atom that no edge points at: its dG blocks are
+    exactly zero, like every slot above 0."""
+    dims = Dims(nkz=7, ne=70, nqz=7, nw=10, na=6, nb=2, norb=10, g_slots=2)
+    print(f"[gpu] backward parity dims={dims.as_tuple()} (energy ranges, unreached atom)", flush=True)
+    inp = _rand(dims, 11)
+    inp["nbr"] = np.array([[1, 2], [2, 3], [3, 4], [4, 5], [5, 1], [1, 3]], dtype=np.int32)
+    alpha = -0.7 + 0.3j
+    gS = _gS(inp["W"])
+    t = {k: torch.from_numpy(v).cuda() for k, v in inp.items()}
+    dG, dD, ddH = sse.backward(t["G"], t["D"], t["dH"], t["nbr"], torch.from_numpy(gS).cuda(), alpha=alpha)
+    rG, rD, rH = oracle.sse_backward(dims, inp["G"], inp["D"], inp["dH"], inp["nbr"], gS, alpha=alpha)
+    for name, got, ref in (("dG", dG, rG), ("dD", dD, rD), ("ddH", ddH, rH)):
+        err = _rel(got.cpu().numpy(), ref)
+        print(f"  {name} rel err {err:.3e}", flush=True)
+        assert err <= 1e-12, name
+    assert torch.count_nonzero(dG[:, :, 0]) == 0
+    assert torch.count_nonzero(dG[:, :, :, 1:]) == 0
+
+
 @pytest.mark.parametrize("dims,seed", [SMALL[1], SMALL[2]], ids=["norb10", "odd_nb"])
 def test_out_of_range_neighbour_has_no_terms(dims, seed):
     """An entry of nbr outside [0, na) contributes no terms: the gradients equal
