@@ -73,20 +73,20 @@ struct BwdCfg {
     static constexpr int AR = 3 * NORB;       // rows (m, r) of d gradH
     static constexpr int KB = 2 * EP * K2;    // K rows of the d gradH terms (U half, T^H half)
     // LDS (doubles)
-    static constexpr int L_W = KC * MPAD;          // W of one momentum [w, re/im][ep, r, c]
+    static constexpr int L_W = KC * MPAD;          // W of one momentum [w, re/im][ep, r, c] (two buffers)
     static constexpr int L_DC = NKZ * NW * 9 * 4;  // embedded Dc [q][w][ij][4]
     static constexpr int L_Y = EP * 9 * NN * 2;    // Y of one momentum [ep][ij][r][c] complex
     static constexpr int L_U = EP * 3 * NN * 2;    // U and T^H [ep][m][r][c] complex
     static constexpr int L_TA = KA * TW;           // embedded A [j, c, re/im][c', re/im]
-    static constexpr int L_TB = KB * TW;           // embedded conj(B)^T and B
-    static constexpr size_t LDS_BYTES = 8 * (size_t)(L_W + L_DC + L_Y + 2 * L_U + L_TA + L_TB);
+    static constexpr int L_TB = KB * TW;           // embedded conj(B)^T and B (two buffers)
+    static constexpr size_t LDS_BYTES = 8 * (size_t)(2 * L_W + L_DC + L_Y + 2 * L_U + L_TA + 2 * L_TB);
     static_assert(NT == WAVES, "one column tile of the main GEMM per wave");
     static_assert(KC % 4 == 0 && K2 % 4 == 0, "a K step never straddles a frequency pair or a block j");
     static_assert(K2 <= TW, "table width");
     static constexpr int NPAIR = (PR + 15) / 16 * 2;  // (row tile, column tile) pairs of U and T^H
     static_assert((K2 + 15) / 16 == 2, "two column tiles in the small products");
     static_assert(NPAIR == 8 || NPAIR == 4, "U and T^H: both products of one pair per wave, or one of them");
-    static_assert((GR + 15) / 16 <= 2 && (AR + 15) / 16 <= 2, "dG and d gradH terms: four tiles each");
+    static_assert(GR <= 16 && (AR + 15) / 16 == 2, "dG term: two tiles (waves 2, 3); d gradH: four (waves 0, 1, 4, 5)");
     static_assert(NN % 4 == 0, "the four rows of an output lane group share one energy");
     static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
 };
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(512) void bwd_mfma_kernel(Dims d, const double* __r
     constexpr int NN = C::NN, K2 = C::K2, TW = C::TW, MPAD = C::MPAD;
     extern __shared__ double lds[];
     double* sW = lds;
-    double* sDc = sW + C::L_W;
+    double* sDc = sW + 2 * C::L_W;
     double* sY = sDc + C::L_DC;
     double* sU = sY + C::L_Y;
     double* sT = sU + C::L_U;
@@ -144,6 +144,9 @@ __global__ __launch_bounds__(512) void bwd_mfma_kernel(Dims d, const double* __r
     // W items of this thread: (w, ep, r c) = tid + THREADS u
     constexpr int NITEM = NW * C::EP * NN;
     constexpr int NU = (NITEM + C::THREADS - 1) / C::THREADS;
+    // B items of this thread: (k', ep, p q) = tid + THREADS u
+    constexpr int NBITEM = NKZ * C::EP * NN;
+    constexpr int NUB = (NBITEM + C::THREADS - 1) / C::THREADS;
 
     f64x4 dacc = {0.0, 0.0, 0.0, 0.0};  // d gradH tile of waves 4..7, per edge
     for (int32_t ei = e_lo; ei < e_hi; ++ei) {
@@ -173,12 +176,32 @@ __global__ __launch_bounds__(512) void bwd_mfma_kernel(Dims d, const double* __r
         }
         dacc = f64x4{0.0, 0.0, 0.0, 0.0};
         const double* gA = gS + 2 * off_S(d, 0, 0, a);  // g of atom a at (k, E) = 0
+        // dG entries of this lane in the dG-term waves (rows (ep, x), columns (u, re/im)):
+        // the first edge writes them, later edges add to the previous edge's
+        // values, read one round ahead
+        const int64_t g_k = 2 * d.ne * d.na * d.gs * NN;  // one momentum further in dG
+        int64_t g_off[4];
+        bool g_ok[4];
+        double gprev[4];
+        auto set_prev = [&](int E0) {
+            const int cl = 16 * (wave - 2) + l16;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int orow = 4 * v + l4, o_ep = orow / NORB, o_x = orow % NORB;
+                g_ok[v] = orow < C::GR && cl < K2 && E0 + o_ep < NE;
+                g_off[v] = 2 * (off_G(d, 0, g_ok[v] ? E0 + o_ep : 0, b) + o_x * NORB) + cl;
+            }
+        };
+        auto load_prev = [&](int kp) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) gprev[v] = (ei != e_lo && g_ok[v]) ? dG[g_off[v] + g_k * kp] : 0.0;
+        };
         const int64_t stride_e = 2 * d.na * NN, stride_k = stride_e * d.ne;
 
-        for (int E0 = E_lo; E0 < E_hi; E0 += C::EP) {
-            // gather state of the W items: relative offsets of the two shifted blocks
-            int64_t rel_p[NU], rel_m[NU];
-            bool ok_p[NU], ok_m[NU];
+        // W items of this thread for the energies from E0: offsets of the two shifted blocks
+        int64_t rel_p[NU], rel_m[NU];
+        bool ok_p[NU], ok_m[NU];
+        auto set_items = [&](int E0) {
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
                 const int i = tid + C::THREADS * u;
@@ -190,56 +213,85 @@ __global__ __launch_bounds__(512) void bwd_mfma_kernel(Dims d, const double* __r
                 rel_p[u] = (int64_t)(E + w) * stride_e + 2 * rc;
                 rel_m[u] = (int64_t)(E - w) * stride_e + 2 * rc;
             }
-            cd gp[NU], gm[NU];
-            auto gather = [&](int k) {
+        };
+        cd gp[NU], gm[NU];
+        auto gather = [&](int k) {
 #pragma unroll
-                for (int u = 0; u < NU; ++u) {
-                    const double* pp = ok_p[u] ? gA + k * stride_k + rel_p[u] : bwdm_zero;
-                    const double* pm = ok_m[u] ? gA + k * stride_k + rel_m[u] : bwdm_zero;
-                    const double2 vp = *reinterpret_cast<const double2*>(pp);
-                    const double2 vm = *reinterpret_cast<const double2*>(pm);
-                    gp[u] = cd{vp.x, vp.y};
-                    gm[u] = cd{vm.x, vm.y};
-                }
-            };
-            auto store_w = [&]() {
+            for (int u = 0; u < NU; ++u) {
+                const double* pp = ok_p[u] ? gA + k * stride_k + rel_p[u] : bwdm_zero;
+                const double* pm = ok_m[u] ? gA + k * stride_k + rel_m[u] : bwdm_zero;
+                const double2 vp = *reinterpret_cast<const double2*>(pp);
+                const double2 vm = *reinterpret_cast<const double2*>(pm);
+                gp[u] = cd{vp.x, vp.y};
+                gm[u] = cd{vm.x, vm.y};
+            }
+        };
+        auto store_w = [&](int buf) {
+            double* w = sW + buf * C::L_W;
 #pragma unroll
-                for (int u = 0; u < NU; ++u) {
-                    const int i = tid + C::THREADS * u;
-                    if (i < NITEM) {
-                        const int row = i % (NN * C::EP), wi = i / (NN * C::EP);
-                        sW[(2 * wi) * MPAD + row] = gp[u].re + gm[u].re;
-                        sW[(2 * wi + 1) * MPAD + row] = gp[u].im + gm[u].im;
-                    }
+            for (int u = 0; u < NU; ++u) {
+                const int i = tid + C::THREADS * u;
+                if (i < NITEM) {
+                    const int row = i % (NN * C::EP), wi = i / (NN * C::EP);
+                    w[(2 * wi) * MPAD + row] = gp[u].re + gm[u].re;
+                    w[(2 * wi + 1) * MPAD + row] = gp[u].im + gm[u].im;
                 }
-            };
+            }
+        };
+        // the first momentum of the first energies; later ones are stored in
+        // the product rounds of the energies before
+        set_items(E_lo);
+        gather(0);
+        store_w(0);
+        __syncthreads();
+
+        for (int E0 = E_lo; E0 < E_hi; E0 += C::EP) {
+            // the neighbour's G blocks of every momentum at these energies, read
+            // during the GEMM and staged as tables in the product rounds
+            cd bpre[NUB];
+#pragma unroll
+            for (int u = 0; u < NUB; ++u) {
+                const int x = tid + C::THREADS * u;
+                const int kp = x / (C::EP * NN), ep = (x / NN) % C::EP, pq = x % NN;
+                bpre[u] = cd{0.0, 0.0};
+                if (x < NBITEM && E0 + ep < NE) bpre[u] = cload(G, off_G(d, kp, E0 + ep, b) + pq);
+            }
+
+            // the previous edge's dG of the first momentum (added to in the first round)
+            if (dG && (wave == 2 || wave == 3)) {
+                set_prev(E0);
+                load_prev(0);
+            }
 
             f64x4 acc[C::MT];
 #pragma unroll
             for (int mt = 0; mt < C::MT; ++mt) acc[mt] = f64x4{0.0, 0.0, 0.0, 0.0};
-            gather(0);
-            store_w();
-            __syncthreads();
+            // momentum k in buffer k & 1: it is written while the other buffer is
+            // read, and the barrier that ends momentum k - 1 orders the two
             for (int k = 0; k < NKZ; ++k) {
                 if (k + 1 < NKZ) gather(k + 1);
                 int q = k - kpc;
                 if (q < 0) q += NKZ;
                 const double* pb = sDc + q * NW * 36 + dc_lane;
+                const double* pa = pa_main + (k & 1) * C::L_W;
 #pragma unroll
                 for (int s = 0; s < C::KS; ++s) {
                     const double bv = pb[72 * s];
 #pragma unroll
-                    for (int mt = 0; mt < C::MT; ++mt) acc[mt] = mma(pa_main[4 * s * MPAD + 16 * mt], bv, acc[mt]);
+                    for (int mt = 0; mt < C::MT; ++mt) acc[mt] = mma(pa[4 * s * MPAD + 16 * mt], bv, acc[mt]);
                 }
-                __syncthreads();  // every wave is done with this momentum's W
-                if (k + 1 < NKZ) {
-                    store_w();
-                    __syncthreads();
-                }
+                if (k + 1 < NKZ) store_w((k + 1) & 1);
+                __syncthreads();
+            }
+            // the first momentum of the next energies, read during the product rounds
+            if (E0 + C::EP < E_hi) {
+                set_items(E0 + C::EP);
+                gather(0);
             }
 
-            // ---- the small products, one momentum k' at a time
-            for (int kp = 0; kp < NKZ; ++kp) {
+            // ---- the small products, one momentum k' at a time.  Stage kp: Y of
+            // momentum kp into sY, the B tables into buffer kp & 1.
+            auto stage = [&](int kp) {
                 // Y of momentum kp from the columns that carry it
                 // (row 16 mt + 4 v + l4 lies in energy (16 mt + 4 v) / NN: NN is a multiple of 4)
                 if (kpc == kp && col < C::NCOL) {
@@ -257,23 +309,29 @@ __global__ __launch_bounds__(512) void bwd_mfma_kernel(Dims d, const double* __r
                 }
                 // conj(B)^T at rows (ep, c', re/im), columns (c, re/im); B at rows
                 // KB/2 + (ep, q, re/im), columns (c, re/im)
-                for (int x = tid; x < C::EP * NN; x += C::THREADS) {
-                    const int ep = x / NN, p = (x % NN) / NORB, qq = x % NORB;
-                    const int E = E0 + ep;
-                    cd v{0.0, 0.0};
-                    if (E < NE) v = cload(G, off_G(d, kp, E, b) + p * NORB + qq);
-                    double* o1 = sTB + (ep * K2 + 2 * qq) * TW + 2 * p;
-                    o1[0] = v.re;
-                    o1[1] = -v.im;
-                    o1[TW] = v.im;
-                    o1[TW + 1] = v.re;
-                    double* o2 = sTB + (C::EP * K2 + ep * K2 + 2 * p) * TW + 2 * qq;
-                    o2[0] = v.re;
-                    o2[1] = v.im;
-                    o2[TW] = -v.im;
-                    o2[TW + 1] = v.re;
+                double* tb = sTB + (kp & 1) * C::L_TB;
+#pragma unroll
+                for (int u = 0; u < NUB; ++u) {
+                    const int x = tid + C::THREADS * u;
+                    if (x < NBITEM && x / (C::EP * NN) == kp) {
+                        const int ep = (x / NN) % C::EP, p = (x % NN) / NORB, qq = x % NORB;
+                        const cd v = bpre[u];
+                        double* o1 = tb + (ep * K2 + 2 * qq) * TW + 2 * p;
+                        o1[0] = v.re;
+                        o1[1] = -v.im;
+                        o1[TW] = v.im;
+                        o1[TW + 1] = v.re;
+                        double* o2 = tb + (C::EP * K2 + ep * K2 + 2 * p) * TW + 2 * qq;
+                        o2[0] = v.re;
+                        o2[1] = v.im;
+                        o2[TW] = -v.im;
+                        o2[TW + 1] = v.re;
+                    }
                 }
-                __syncthreads();
+            };
+            stage(0);
+            __syncthreads();
+            for (int kp = 0; kp < NKZ; ++kp) {
                 // U_m[ep][r][c'] = sum_{j,c} Y_mj[r][c] A_j[c][c'] and
                 // T^H_m[ep][p][q] = sum_{i,r} conj(Y_im[r][p]) A_i[r][q]: rows (ep, m, r)
                 {
@@ -308,11 +366,11 @@ __global__ __launch_bounds__(512) void bwd_mfma_kernel(Dims d, const double* __r
                     }
                 }
                 __syncthreads();
-                if (wave < 4) {
+                if (wave == 2 || wave == 3) {
                     // dG[ep][x][u] (+)= sum_{j,c} conj(T^H_j[ep][c][x]) A_j[c][u]: rows (ep, x)
-                    if (dG && wave < (C::GR + 15) / 16 * 2) {
-                        const int mt = wave >> 1, nt = wave & 1;
-                        int row = 16 * mt + l16;
+                    if (dG) {
+                        const int nt = wave - 2;
+                        int row = l16;
                         if (row >= C::GR) row = C::GR - 1;
                         const int ep = row / NORB, x = row % NORB;
                         const double* pa = sT + (ep * 3 * NN + x) * 2 + (l4 >> 1) * 2 * NORB + (l4 & 1);
@@ -324,26 +382,22 @@ __global__ __launch_bounds__(512) void bwd_mfma_kernel(Dims d, const double* __r
                             const int t0 = 4 * s, j = t0 / K2, rem = t0 % K2;
                             cg = mma(neg_if(pa[j * 2 * NN + rem * NORB], neg), pb[t0 * TW], cg);
                         }
-                        const int cl = 16 * nt + l16;
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const int orow = 16 * mt + 4 * v + l4;
-                            const int o_ep = orow / NORB, o_x = orow % NORB;
-                            if (orow < C::GR && cl < K2 && E0 + o_ep < NE) {
-                                double* p = dG + 2 * (off_G(d, kp, E0 + o_ep, b) + o_x * NORB) + cl;
-                                *p = ei == e_lo ? cg[v] : *p + cg[v];
-                            }
-                        }
+                        for (int v = 0; v < 4; ++v)
+                            if (g_ok[v]) dG[g_off[v] + g_k * kp] = gprev[v] + cg[v];
+                        if (kp + 1 < NKZ) load_prev(kp + 1);
                     }
-                } else if (dApart) {
+                } else if (dApart && wave < 6) {
                     // dA_m[r][c] += sum_{ep,c'} U_m[ep][r][c'] conj(B_ep[c][c'])
-                    //             + sum_{ep,q} T^H_m[ep][r][q] B_ep[q][c]: rows (m, r)
-                    const int w4 = wave - 4, mt = w4 >> 1, nt = w4 & 1;
+                    //             + sum_{ep,q} T^H_m[ep][r][q] B_ep[q][c]: rows (m, r);
+                    // waves 0, 1, 4, 5, so that each SIMD carries at most two of the
+                    // four tiles of this phase
+                    const int w4 = (wave & 1) + 2 * (wave >> 2), mt = w4 >> 1, nt = w4 & 1;
                     int row = 16 * mt + l16;
                     if (row >= C::AR) row = C::AR - 1;
                     const int m = row / NORB, r = row % NORB;
                     const int arow = (m * NN + r * NORB) * 2 + l4;
-                    const double* pb = sTB + l4 * TW + 16 * nt + l16;
+                    const double* pb = sTB + (kp & 1) * C::L_TB + l4 * TW + 16 * nt + l16;
 #pragma unroll
                     for (int s = 0; s < C::KB / 4; ++s) {
                         const int t0 = 4 * s, half = t0 / (C::EP * K2), th = t0 % (C::EP * K2);
@@ -352,12 +406,18 @@ __global__ __launch_bounds__(512) void bwd_mfma_kernel(Dims d, const double* __r
                         dacc = mma(src[arow + ep * 6 * NN + rem], pb[t0 * TW], dacc);
                     }
                 }
-                __syncthreads();  // the tables and staged blocks of this momentum are free
+                // the next momentum's Y and tables (sY, sU and sT are no longer read by
+                // this round; the other table buffer was last read a round ago), and
+                // in the last round the first W of the next energies (buffer 0, last
+                // read by the GEMM's final momentum)
+                if (kp + 1 < NKZ) stage(kp + 1);
+                else if (E0 + C::EP < E_hi) store_w(0);
+                __syncthreads();
             }
         }
         // this energy range's share of the edge's d gradH
-        if (dApart && wave >= 4) {
-            const int w4 = wave - 4, mt = w4 >> 1, nt = w4 & 1;
+        if (dApart && (wave < 2 || wave == 4 || wave == 5)) {
+            const int w4 = (wave & 1) + 2 * (wave >> 2), mt = w4 >> 1, nt = w4 & 1;
             const int cl = 16 * nt + l16;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
