@@ -121,8 +121,9 @@ const char* sse_last_error(void);
 
 /*
  * Bytes of workspace a call needs.  op = 0 for sse_forward with the given
- * precision, 1 for sse_backward, 2 for sse_combine_d (precision ignored for
- * 1 and 2).
+ * precision, 1 for sse_backward and sse_backward_signed with every gradient
+ * (enough for either; a call without ddH needs less, see sse_backward), 2 for
+ * sse_combine_d (precision ignored for 1 and 2).
  */
 int sse_workspace_bytes(const sse_dims* dims, int precision, int op, size_t* bytes);
 
@@ -199,11 +200,15 @@ int sse_forward_ex(const sse_dims* dims, const double* G, const double* Dp, cons
  *   ddH[a,n,i]        += conj(alpha d) g A_j B^H
  *   ddH[a,n,j]        += alpha d g^H A_i B
  * Shifted G blocks are re-gathered, not stored.  The workspace
- * (sse_workspace_bytes(dims, 0, 1) bytes) holds the reverse neighbour
- * adjacency and, per momentum kz', every edge's share of dL/d(dH)
- * (16 * nkz * na * nb * 3 * norb^2 bytes), added in kz' order, so results are
- * bitwise reproducible.  An entry of nbr outside [0, na) has no terms: its
- * ddH block is zero.
+ * (sse_workspace_bytes(dims, 0, 1) bytes suffice for every call) holds the
+ * reverse neighbour adjacency (4 * (3 na + 1 + na * nb) bytes, rounded up to
+ * 256) and, if ddH is wanted, S shares of every edge's dL/d(dH)
+ * (16 * S * na * nb * 3 * norb^2 bytes), added in share order, so results are
+ * bitwise reproducible: S = ceil(ne / 32) (one per range of 32 energies) on the
+ * matrix-core shape (norb = 10, nkz = nqz = 7, nw = 10), S = nkz (one per
+ * momentum) otherwise and in sse_backward_signed.  A smaller workspace than
+ * this call uses is refused with SSE_ERR_WORKSPACE.  An entry of nbr outside
+ * [0, na) has no terms: its ddH block is zero.
  */
 int sse_backward(const sse_dims* dims, const double* G, const double* D, const double* dH,
                  const int32_t* nbr, double alpha_re, double alpha_im, const double* dSigma,
@@ -229,10 +234,13 @@ int sse_backward_signed(const sse_dims* dims, const double* G, const double* Dp,
  * of the library (sse_noalloc_scratch_bytes() bytes, 64 MiB, held by every GPU
  * the library runs on until the process ends) instead of a caller-provided
  * buffer.  Calls no hipMalloc, hipFree or allocating routine.  Dims whose
- * sse_backward workspace exceeds the array are rejected with
- * SSE_ERR_WORKSPACE before anything is launched (at Nkz = 7, Norb = 10, Nb = 4
- * the d(dH) shares take 16 * Nkz * Na * Nb * 3 * Norb^2 bytes: about 4,900
- * atoms with ddH, far more without it).  Every call on one GPU uses that GPU's
+ * workspace for this call exceeds the array are rejected with
+ * SSE_ERR_WORKSPACE before anything is launched: the reverse adjacency takes
+ * 4 * (3 Na + 1 + Na * Nb) bytes (rounded up to 256), and with ddH the d(dH)
+ * shares 16 * S * Na * Nb * 3 * Norb^2 more, S = ceil(NE / 32)
+ * on the matrix-core shape (Norb = 10, Nkz = Nqz = 7, Nw = 10), S = Nkz otherwise
+ * (at Nkz = 7, Norb = 10, Nb = 4, NE <= 224: about 500 atoms with ddH, about
+ * 2.4 million without it).  Every call on one GPU uses that GPU's
  * array (the current device's): calls that overlap on one GPU race.  The
  * kernels rewrite every part of the array they read, so no clearing is needed
  * between calls.  Other arguments and errors as for sse_backward.

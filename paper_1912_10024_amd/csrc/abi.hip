@@ -208,8 +208,8 @@ int backward_impl(const sse_dims* dims, const double* G, const double* Dp, const
     if (!G || !Dp || !Dm || !dH || !nbr || !dSigma) return fail(SSE_ERR_NULL, "an input pointer is NULL");
     const sse::Dims d = sse::to_dims(*dims);
     if (!sse::bwd_supported(d)) return fail(SSE_ERR_DIMS, "no adjoint kernel for these dims");
-    size_t need = 0;
-    sse_workspace_bytes(dims, SSE_FP64, 1, &need);
+    // what this call uses (sse_workspace_bytes covers every gradient of either form)
+    const size_t need = sse::bwd_workspace_bytes_for(d, signed_form, ddH != nullptr);
     if (workspace == nullptr || workspace_bytes < need)
         return fail(SSE_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace_bytes);
     if (!dG && !dDp && !dDm && !ddH) return ok();

@@ -108,9 +108,12 @@ static bool bwd_use_mfma(const Dims& d, bool signed_form) {
 static int64_t bwd_shares(const Dims& d, bool signed_form) {
     return bwd_use_mfma(d, signed_form) ? bwd_mfma_shares(d) : d.nkz;
 }
+size_t bwd_workspace_bytes_for(const Dims& d, bool signed_form, bool with_dh) {
+    return bwd_csr_bytes(d) +
+           (with_dh ? sizeof(cd) * (size_t)(bwd_shares(d, signed_form) * d.na * d.nb * 3 * d.norb * d.norb) : 0);
+}
 size_t bwd_workspace_bytes(const Dims& d) {
-    const int64_t shares = std::max(bwd_shares(d, false), bwd_shares(d, true));
-    return bwd_csr_bytes(d) + sizeof(cd) * (size_t)(shares * d.na * d.nb * 3 * d.norb * d.norb);
+    return std::max(bwd_workspace_bytes_for(d, false, true), bwd_workspace_bytes_for(d, true, true));
 }
 
 // --------------------------------------------------------------- W and Y of one source point

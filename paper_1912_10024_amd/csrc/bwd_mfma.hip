@@ -44,9 +44,21 @@ __device__ __forceinline__ double neg_if(double x, bool neg) {
     return __longlong_as_double(__double_as_longlong(x) ^ (neg ? (long long)0x8000000000000000ull : 0ll));
 }
 
-// a zero element read in place of g blocks outside the energy grid (never
-// written; not const, so it shares the global address space with g)
-__device__ double bwdm_zero[2] = {0.0, 0.0};
+// A chain of NS dependent matrix instructions on one accumulator, its operands
+// read (LDS) up front in step order; the scheduler interleaves the reads with
+// the chain as registers allow.
+template <int NS, class FA, class FB>
+__device__ __forceinline__ f64x4 mma_chain(FA fa, FB fb, f64x4 c) {
+    double a[NS], b[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        a[s] = fa(s);
+        b[s] = fb(s);
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) c = mma(a[s], b[s], c);
+    return c;
+}
 
 }  // namespace
 
@@ -67,7 +79,8 @@ struct BwdCfg {
     // small products: K rows (j, c, re/im) per block j, table width (c', re/im) padded
     static constexpr int K2 = 2 * NORB;
     static constexpr int KA = 3 * K2;
-    static constexpr int TW = 32;
+    static constexpr int TW = 40;  // row stride of the tables: the four rows of an operand read use
+                                   // the two halves of the banks
     static constexpr int PR = EP * 3 * NORB;  // rows (ep, m, r) of U and T^H
     static constexpr int GR = EP * NORB;      // rows (ep, x) of the dG term
     static constexpr int AR = 3 * NORB;       // rows (m, r) of d gradH
@@ -75,7 +88,10 @@ struct BwdCfg {
     // LDS (doubles)
     static constexpr int L_W = KC * MPAD;          // W of one momentum [w, re/im][ep, r, c] (two buffers)
     static constexpr int L_DC = NKZ * NW * 9 * 4;  // embedded Dc [q][w][ij][4]
-    static constexpr int L_Y = EP * 9 * NN * 2;    // Y of one momentum [ep][ij][r][c] complex
+    // Y of one momentum [ep][ij][r][c] complex, YB doubles per (ep, ij) block: the
+    // padding spreads the rows (m, r) of an operand read over the banks
+    static constexpr int YB = 2 * NN + 12;
+    static constexpr int L_Y = EP * 9 * YB;
     static constexpr int L_U = EP * 3 * NN * 2;    // U and T^H [ep][m][r][c] complex
     static constexpr int L_TA = KA * TW;           // embedded A [j, c, re/im][c', re/im]
     static constexpr int L_TB = KB * TW;           // embedded conj(B)^T and B (two buffers)
@@ -207,23 +223,22 @@ __global__ __launch_bounds__(512) void bwd_mfma_kernel(Dims d, const double* __r
                 const int i = tid + C::THREADS * u;
                 const int rc = i % NN, ep = (i / NN) % C::EP, w = i / (NN * C::EP) + 1;
                 const int E = E0 + ep;
-                const bool in = i < NITEM && E < NE;
+                const bool in = i < NITEM && E < NE;  // i >= NITEM: w beyond NW, never in
                 ok_p[u] = in && E + w < NE;
                 ok_m[u] = in && E - w >= 0;
-                rel_p[u] = (int64_t)(E + w) * stride_e + 2 * rc;
-                rel_m[u] = (int64_t)(E - w) * stride_e + 2 * rc;
+                // energies outside the grid read energy 0 of the atom (in bounds) and count as zero
+                rel_p[u] = (int64_t)(ok_p[u] ? E + w : 0) * stride_e + 2 * rc;
+                rel_m[u] = (int64_t)(ok_m[u] ? E - w : 0) * stride_e + 2 * rc;
             }
         };
         cd gp[NU], gm[NU];
         auto gather = [&](int k) {
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
-                const double* pp = ok_p[u] ? gA + k * stride_k + rel_p[u] : bwdm_zero;
-                const double* pm = ok_m[u] ? gA + k * stride_k + rel_m[u] : bwdm_zero;
-                const double2 vp = *reinterpret_cast<const double2*>(pp);
-                const double2 vm = *reinterpret_cast<const double2*>(pm);
-                gp[u] = cd{vp.x, vp.y};
-                gm[u] = cd{vm.x, vm.y};
+                const double2 vp = *reinterpret_cast<const double2*>(gA + k * stride_k + rel_p[u]);
+                const double2 vm = *reinterpret_cast<const double2*>(gA + k * stride_k + rel_m[u]);
+                gp[u] = ok_p[u] ? cd{vp.x, vp.y} : cd{0.0, 0.0};
+                gm[u] = ok_m[u] ? cd{vm.x, vm.y} : cd{0.0, 0.0};
             }
         };
         auto store_w = [&](int buf) {
@@ -274,11 +289,23 @@ __global__ __launch_bounds__(512) void bwd_mfma_kernel(Dims d, const double* __r
                 if (q < 0) q += NKZ;
                 const double* pb = sDc + q * NW * 36 + dc_lane;
                 const double* pa = pa_main + (k & 1) * C::L_W;
+                // operands of K step s + 1 are read while the instructions of step s run
+                double an[C::MT], bn = pb[0];
+#pragma unroll
+                for (int mt = 0; mt < C::MT; ++mt) an[mt] = pa[16 * mt];
 #pragma unroll
                 for (int s = 0; s < C::KS; ++s) {
-                    const double bv = pb[72 * s];
+                    double ac[C::MT];
 #pragma unroll
-                    for (int mt = 0; mt < C::MT; ++mt) acc[mt] = mma(pa[4 * s * MPAD + 16 * mt], bv, acc[mt]);
+                    for (int mt = 0; mt < C::MT; ++mt) ac[mt] = an[mt];
+                    const double bc = bn;
+                    if (s + 1 < C::KS) {
+#pragma unroll
+                        for (int mt = 0; mt < C::MT; ++mt) an[mt] = pa[4 * (s + 1) * MPAD + 16 * mt];
+                        bn = pb[72 * (s + 1)];
+                    }
+#pragma unroll
+                    for (int mt = 0; mt < C::MT; ++mt) acc[mt] = mma(ac[mt], bc, acc[mt]);
                 }
                 if (k + 1 < NKZ) store_w((k + 1) & 1);
                 __syncthreads();
@@ -295,7 +322,7 @@ __global__ __launch_bounds__(512) void bwd_mfma_kernel(Dims d, const double* __r
                 // Y of momentum kp from the columns that carry it
                 // (row 16 mt + 4 v + l4 lies in energy (16 mt + 4 v) / NN: NN is a multiple of 4)
                 if (kpc == kp && col < C::NCOL) {
-                    double* py = sY + ijc * NN * 2 + ccc + 2 * l4;
+                    double* py = sY + ijc * C::YB + ccc + 2 * l4;
 #pragma unroll
                     for (int mt = 0; mt < C::MT; ++mt)
 #pragma unroll
@@ -303,7 +330,7 @@ __global__ __launch_bounds__(512) void bwd_mfma_kernel(Dims d, const double* __r
                             const int r0 = 16 * mt + 4 * v;
                             if (r0 < C::MROWS) {
                                 const int ep = r0 / NN;
-                                py[(ep * 9 * NN + r0 - ep * NN) * 2] = acc[mt][v];
+                                py[ep * 9 * C::YB + (r0 - ep * NN) * 2] = acc[mt][v];
                             }
                         }
                 }
@@ -341,28 +368,34 @@ __global__ __launch_bounds__(512) void bwd_mfma_kernel(Dims d, const double* __r
                     int row = 16 * mt + l16;
                     if (row >= C::PR) row = C::PR - 1;  // padding rows: any in-bounds row
                     const int ep = row / (3 * NORB), m = (row / NORB) % 3, r = row % NORB;
-                    const double* pa1 = sY + ((ep * 9 + m * 3) * NN + r * NORB) * 2 + l4;
-                    const double* pa2 = sY + ((ep * 9 + m) * NN + r) * 2 + (l4 >> 1) * 2 * NORB + (l4 & 1);
+                    const double* pa1 = sY + (ep * 9 + m * 3) * C::YB + r * NORB * 2 + l4;
+                    const double* pa2 = sY + (ep * 9 + m) * C::YB + 2 * r + (l4 >> 1) * 2 * NORB + (l4 & 1);
                     const double* pb = sTA + l4 * TW + 16 * nt + l16;
                     const bool neg = (l4 & 1) != 0;
-                    f64x4 cu = {0.0, 0.0, 0.0, 0.0}, ct = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                    for (int s = 0; s < C::KA / 4; ++s) {
-                        const int t0 = 4 * s, j = t0 / K2, rem = t0 % K2;
-                        const double bv = pb[t0 * TW];
-                        if (do_u) cu = mma(pa1[j * 2 * NN + rem], bv, cu);
-                        if (do_t) ct = mma(neg_if(pa2[j * 6 * NN + rem * NORB], neg), bv, ct);
-                    }
                     const int cl = 16 * nt + l16;
+                    // one straight-line product per path (the choice is uniform per wave)
+                    auto store_tile = [&](double* dst, const f64x4& c) {
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int orow = 16 * mt + 4 * v + l4;
-                        if (orow < C::PR && cl < K2) {
-                            const int o_ep = orow / (3 * NORB), o_m = (orow / NORB) % 3, o_r = orow % NORB;
-                            const int o = ((o_ep * 3 + o_m) * NN + o_r * NORB) * 2 + cl;
-                            if (do_u) sU[o] = cu[v];
-                            if (do_t) sT[o] = ct[v];
+                        for (int v = 0; v < 4; ++v) {
+                            const int orow = 16 * mt + 4 * v + l4;
+                            if (orow < C::PR && cl < K2) {
+                                const int o_ep = orow / (3 * NORB), o_m = (orow / NORB) % 3, o_r = orow % NORB;
+                                dst[((o_ep * 3 + o_m) * NN + o_r * NORB) * 2 + cl] = c[v];
+                            }
                         }
+                    };
+                    const f64x4 zero = {0.0, 0.0, 0.0, 0.0};
+                    auto b_of = [&](int s) { return pb[4 * s * TW]; };
+                    if (do_u) {
+                        const f64x4 cu = mma_chain<C::KA / 4>(
+                            [&](int s) { return pa1[(4 * s / K2) * C::YB + (4 * s) % K2]; }, b_of, zero);
+                        store_tile(sU, cu);
+                    }
+                    if (do_t) {
+                        const f64x4 ct = mma_chain<C::KA / 4>(
+                            [&](int s) { return neg_if(pa2[(4 * s / K2) * 3 * C::YB + ((4 * s) % K2) * NORB], neg); },
+                            b_of, zero);
+                        store_tile(sT, ct);
                     }
                 }
                 __syncthreads();
@@ -376,12 +409,9 @@ __global__ __launch_bounds__(512) void bwd_mfma_kernel(Dims d, const double* __r
                         const double* pa = sT + (ep * 3 * NN + x) * 2 + (l4 >> 1) * 2 * NORB + (l4 & 1);
                         const double* pb = sTA + l4 * TW + 16 * nt + l16;
                         const bool neg = (l4 & 1) != 0;
-                        f64x4 cg = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                        for (int s = 0; s < C::KA / 4; ++s) {
-                            const int t0 = 4 * s, j = t0 / K2, rem = t0 % K2;
-                            cg = mma(neg_if(pa[j * 2 * NN + rem * NORB], neg), pb[t0 * TW], cg);
-                        }
+                        const f64x4 cg = mma_chain<C::KA / 4>(
+                            [&](int s) { return neg_if(pa[(4 * s / K2) * 2 * NN + ((4 * s) % K2) * NORB], neg); },
+                            [&](int s) { return pb[4 * s * TW]; }, f64x4{0.0, 0.0, 0.0, 0.0});
 #pragma unroll
                         for (int v = 0; v < 4; ++v)
                             if (g_ok[v]) dG[g_off[v] + g_k * kp] = gprev[v] + cg[v];
@@ -398,13 +428,12 @@ __global__ __launch_bounds__(512) void bwd_mfma_kernel(Dims d, const double* __r
                     const int m = row / NORB, r = row % NORB;
                     const int arow = (m * NN + r * NORB) * 2 + l4;
                     const double* pb = sTB + (kp & 1) * C::L_TB + l4 * TW + 16 * nt + l16;
-#pragma unroll
-                    for (int s = 0; s < C::KB / 4; ++s) {
-                        const int t0 = 4 * s, half = t0 / (C::EP * K2), th = t0 % (C::EP * K2);
-                        const int ep = th / K2, rem = th % K2;
-                        const double* src = half ? sT : sU;
-                        dacc = mma(src[arow + ep * 6 * NN + rem], pb[t0 * TW], dacc);
-                    }
+                    dacc = mma_chain<C::KB / 4>(
+                        [&](int s) {
+                            const int t0 = 4 * s, th = t0 % (C::EP * K2);
+                            return (t0 / (C::EP * K2) ? sT : sU)[arow + (th / K2) * 6 * NN + th % K2];
+                        },
+                        [&](int s) { return pb[4 * s * TW]; }, dacc);
                 }
                 // the next momentum's Y and tables (sY, sU and sT are no longer read by
                 // this round; the other table buffer was last read a round ago), and

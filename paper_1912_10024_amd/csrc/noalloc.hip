@@ -9,8 +9,8 @@
 // Nothing here allocates.  Every call on a GPU shares that GPU's array, so
 // calls that overlap on one GPU race; the kernels overwrite every part of the
 // array they read (the reverse adjacency is built by a zeroing kernel, then
-// counts, scan and fill; every per-momentum grad H share that the reduction
-// reads is written first), so no clearing between calls is needed.
+// counts, scan and fill; every d grad H share that the reduction reads is
+// written first), so no clearing between calls is needed.
 #include <mutex>
 
 #include "sse_kernels.h"
@@ -52,9 +52,11 @@ int sse_backward_noalloc(const sse_dims* dims, const double* G, const double* D,
                          const int32_t* nbr, double alpha_re, double alpha_im, const double* dSigma, double* dG,
                          double* dD, double* ddH, void* stream) {
     // argument checks as for sse_backward (its messages via sse_last_error)
-    size_t need = 0;
-    int rc = sse_workspace_bytes(dims, SSE_FP64, 1, &need);
+    size_t full = 0;  // (validates dims)
+    int rc = sse_workspace_bytes(dims, SSE_FP64, 1, &full);
     if (rc) return rc;
+    // the part of the workspace this call uses: without ddH, the reverse adjacency only
+    const size_t need = sse::bwd_workspace_bytes_for(sse::to_dims(*dims), false, ddH != nullptr);
     if (need > kScratchBytes)
         return sse::set_error(SSE_ERR_WORKSPACE, "sse_backward_noalloc: these dims need %zu bytes of workspace, above its %zu",
                               need, kScratchBytes);

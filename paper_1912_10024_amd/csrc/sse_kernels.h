@@ -38,7 +38,9 @@ hipError_t launch_fwd_h16(const Dims& d, int precision, const double* G, const d
 // signed_form: the terms with G at E - w read Dp and feed dDp, those at E + w
 // read Dm and feed dDm; otherwise Dp is the one table and dDp its gradient (Dm,
 // dDm unused).
-size_t bwd_workspace_bytes(const Dims& d);
+size_t bwd_workspace_bytes(const Dims& d);  // enough for either form, with every gradient
+// what one call uses: the reverse adjacency, plus the d gradH shares if that gradient is asked for
+size_t bwd_workspace_bytes_for(const Dims& d, bool signed_form, bool with_dh);
 bool bwd_supported(const Dims& d);
 // dG and d gradH of the one-table form on the matrix cores (Norb = 10, Nkz = Nqz = 7,
 // Nw = 10): one workgroup per (neighbour atom, range of energies), one d gradH

@@ -106,3 +106,13 @@ def pse_formation_flops(d) -> float:
 def pse_flops(d) -> float:
     """Useful fp64 flops of one phonon self-energy call (one of Pi< / Pi>)."""
     return pse_contraction_flops(d) + pse_formation_flops(d)
+
+
+def adjoint_dgdh_flops(d) -> float:
+    """Useful fp64 flops of the dG / d gradH part of one adjoint call: per edge
+    (a, n), momentum k' and energy E', Y_ij = sum_{q,w} conj(alpha D_ij[q,w]) W[k'+q, w, E']
+    (9 Nqz Nw complex products of Norb^2 entries) and the 27 complex Norb^3
+    products built on it: U_m = sum_j Y_mj A_j (9), T_m = sum_i A_i^H Y_im (9),
+    the dG term sum_j T_j A_j (3) and the d gradH terms U_m B^H and T_m^H B (6)."""
+    per = 8.0 * d.norb ** 2 * (9 * d.nqz * d.nw + 27 * d.norb)
+    return per * d.na * d.nb * d.nkz * d.ne

@@ -50,9 +50,16 @@ def test_noalloc_refuses_a_workspace_beyond_its_array():
     need = ctypes.c_size_t(0)
     assert lib.sse_workspace_bytes(ctypes.byref(_lib.SSEDims.of(d)), 0, 1, ctypes.byref(need)) == _lib.SSE_OK
     assert need.value > cap
-    # NULL tensors: the size check comes first (and NULL pointers would be refused
-    # before any launch anyway)
+    # NULL inputs: the size check comes first and reads no pointer, it only asks
+    # whether ddH is wanted (a placeholder that is never dereferenced); NULL
+    # inputs would be refused before any launch anyway
+    ddh_wanted = ctypes.c_void_p(256)
     rc = lib.sse_backward_noalloc(ctypes.byref(_lib.SSEDims.of(d)), None, None, None, None, 0.0, 1.0, None,
-                                  None, None, None, None)
+                                  None, None, ddh_wanted, None)
     assert rc == _lib.SSE_ERR_WORKSPACE
     assert "above its" in _lib.last_error()
+    # without ddH the call needs the reverse adjacency only, which fits: the
+    # size check passes and the NULL inputs are what is refused
+    rc = lib.sse_backward_noalloc(ctypes.byref(_lib.SSEDims.of(d)), None, None, None, None, 0.0, 1.0, None,
+                                  None, None, None, None)
+    assert rc == _lib.SSE_ERR_NULL
