@@ -91,11 +91,11 @@ struct BwdCfg {
     // Y of one momentum [ep][ij][r][c] complex, YB doubles per (ep, ij) block: the
     // padding spreads the rows (m, r) of an operand read over the banks
     static constexpr int YB = 2 * NN + 12;
-    static constexpr int L_Y = EP * 9 * YB;
-    static constexpr int L_U = EP * 3 * NN * 2;    // U and T^H [ep][m][r][c] complex
+    static constexpr int L_Y = EP * 9 * YB;  // (two buffers)
+    static constexpr int L_U = EP * 3 * NN * 2;    // U and T^H [ep][m][r][c] complex (two buffers each)
     static constexpr int L_TA = KA * TW;           // embedded A [j, c, re/im][c', re/im]
     static constexpr int L_TB = KB * TW;           // embedded conj(B)^T and B (two buffers)
-    static constexpr size_t LDS_BYTES = 8 * (size_t)(2 * L_W + L_DC + L_Y + 2 * L_U + L_TA + 2 * L_TB);
+    static constexpr size_t LDS_BYTES = 8 * (size_t)(2 * L_W + L_DC + 2 * L_Y + 4 * L_U + L_TA + 2 * L_TB);
     static_assert(NT == WAVES, "one column tile of the main GEMM per wave");
     static_assert(KC % 4 == 0 && K2 % 4 == 0, "a K step never straddles a frequency pair or a block j");
     static_assert(K2 <= TW, "table width");
@@ -120,9 +120,9 @@ __global__ __launch_bounds__(512) void bwd_mfma_kernel(Dims d, const double* __r
     double* sW = lds;
     double* sDc = sW + 2 * C::L_W;
     double* sY = sDc + C::L_DC;
-    double* sU = sY + C::L_Y;
-    double* sT = sU + C::L_U;
-    double* sTA = sT + C::L_U;
+    double* sU = sY + 2 * C::L_Y;
+    double* sT = sU + 2 * C::L_U;
+    double* sTA = sT + 2 * C::L_U;
     double* sTB = sTA + C::L_TA;
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -208,9 +208,9 @@ __global__ __launch_bounds__(512) void bwd_mfma_kernel(Dims d, const double* __r
                 g_off[v] = 2 * (off_G(d, 0, g_ok[v] ? E0 + o_ep : 0, b) + o_x * NORB) + cl;
             }
         };
-        auto load_prev = [&](int kp) {
+        auto load_prev = [&](int kp, double* dst) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) gprev[v] = (ei != e_lo && g_ok[v]) ? dG[g_off[v] + g_k * kp] : 0.0;
+            for (int v = 0; v < 4; ++v) dst[v] = (ei != e_lo && g_ok[v]) ? dG[g_off[v] + g_k * kp] : 0.0;
         };
         const int64_t stride_e = 2 * d.na * NN, stride_k = stride_e * d.ne;
 
@@ -275,7 +275,7 @@ __global__ __launch_bounds__(512) void bwd_mfma_kernel(Dims d, const double* __r
             // the previous edge's dG of the first momentum (added to in the first round)
             if (dG && (wave == 2 || wave == 3)) {
                 set_prev(E0);
-                load_prev(0);
+                load_prev(0, gprev);
             }
 
             f64x4 acc[C::MT];
@@ -316,13 +316,16 @@ __global__ __launch_bounds__(512) void bwd_mfma_kernel(Dims d, const double* __r
                 gather(0);
             }
 
-            // ---- the small products, one momentum k' at a time.  Stage kp: Y of
-            // momentum kp into sY, the B tables into buffer kp & 1.
-            auto stage = [&](int kp) {
+            // ---- the small products, pipelined over the momenta k'.  Phase kp runs U
+            // and T^H of kp (sY buffer kp & 1 into sU / sT buffer kp & 1), the dG and
+            // d gradH terms of kp - 1 (sU / sT and table buffer (kp - 1) & 1), and
+            // stages Y of kp + 1 and the B tables of kp; one barrier per phase.  Every
+            // buffer a phase writes was last read two phases earlier.
+            auto stage_y = [&](int kp) {
                 // Y of momentum kp from the columns that carry it
                 // (row 16 mt + 4 v + l4 lies in energy (16 mt + 4 v) / NN: NN is a multiple of 4)
                 if (kpc == kp && col < C::NCOL) {
-                    double* py = sY + ijc * C::YB + ccc + 2 * l4;
+                    double* py = sY + (kp & 1) * C::L_Y + ijc * C::YB + ccc + 2 * l4;
 #pragma unroll
                     for (int mt = 0; mt < C::MT; ++mt)
 #pragma unroll
@@ -334,6 +337,8 @@ __global__ __launch_bounds__(512) void bwd_mfma_kernel(Dims d, const double* __r
                             }
                         }
                 }
+            };
+            auto stage_tb = [&](int kp) {
                 // conj(B)^T at rows (ep, c', re/im), columns (c, re/im); B at rows
                 // KB/2 + (ep, q, re/im), columns (c, re/im)
                 double* tb = sTB + (kp & 1) * C::L_TB;
@@ -356,49 +361,51 @@ __global__ __launch_bounds__(512) void bwd_mfma_kernel(Dims d, const double* __r
                     }
                 }
             };
-            stage(0);
-            __syncthreads();
-            for (int kp = 0; kp < NKZ; ++kp) {
-                // U_m[ep][r][c'] = sum_{j,c} Y_mj[r][c] A_j[c][c'] and
-                // T^H_m[ep][p][q] = sum_{i,r} conj(Y_im[r][p]) A_i[r][q]: rows (ep, m, r)
-                {
-                    const int pair = C::NPAIR == 8 ? wave : (wave & 3);
-                    const bool do_u = C::NPAIR == 8 || wave < 4, do_t = C::NPAIR == 8 || wave >= 4;
-                    const int mt = pair >> 1, nt = pair & 1;
-                    int row = 16 * mt + l16;
-                    if (row >= C::PR) row = C::PR - 1;  // padding rows: any in-bounds row
-                    const int ep = row / (3 * NORB), m = (row / NORB) % 3, r = row % NORB;
-                    const double* pa1 = sY + (ep * 9 + m * 3) * C::YB + r * NORB * 2 + l4;
-                    const double* pa2 = sY + (ep * 9 + m) * C::YB + 2 * r + (l4 >> 1) * 2 * NORB + (l4 & 1);
-                    const double* pb = sTA + l4 * TW + 16 * nt + l16;
-                    const bool neg = (l4 & 1) != 0;
-                    const int cl = 16 * nt + l16;
-                    // one straight-line product per path (the choice is uniform per wave)
-                    auto store_tile = [&](double* dst, const f64x4& c) {
+            // U_m[ep][r][c'] = sum_{j,c} Y_mj[r][c] A_j[c][c'] and
+            // T^H_m[ep][p][q] = sum_{i,r} conj(Y_im[r][p]) A_i[r][q]: rows (ep, m, r)
+            auto uv = [&](int kp) {
+                const double* yb = sY + (kp & 1) * C::L_Y;
+                double* ub = sU + (kp & 1) * C::L_U;
+                double* tb = sT + (kp & 1) * C::L_U;
+                const int pair = C::NPAIR == 8 ? wave : (wave & 3);
+                const bool do_u = C::NPAIR == 8 || wave < 4, do_t = C::NPAIR == 8 || wave >= 4;
+                const int mt = pair >> 1, nt = pair & 1;
+                int row = 16 * mt + l16;
+                if (row >= C::PR) row = C::PR - 1;  // padding rows: any in-bounds row
+                const int ep = row / (3 * NORB), m = (row / NORB) % 3, r = row % NORB;
+                const double* pa1 = yb + (ep * 9 + m * 3) * C::YB + r * NORB * 2 + l4;
+                const double* pa2 = yb + (ep * 9 + m) * C::YB + 2 * r + (l4 >> 1) * 2 * NORB + (l4 & 1);
+                const double* pb = sTA + l4 * TW + 16 * nt + l16;
+                const bool neg = (l4 & 1) != 0;
+                const int cl = 16 * nt + l16;
+                // one straight-line product per path (the choice is uniform per wave)
+                auto store_tile = [&](double* dst, const f64x4& c) {
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const int orow = 16 * mt + 4 * v + l4;
-                            if (orow < C::PR && cl < K2) {
-                                const int o_ep = orow / (3 * NORB), o_m = (orow / NORB) % 3, o_r = orow % NORB;
-                                dst[((o_ep * 3 + o_m) * NN + o_r * NORB) * 2 + cl] = c[v];
-                            }
+                    for (int v = 0; v < 4; ++v) {
+                        const int orow = 16 * mt + 4 * v + l4;
+                        if (orow < C::PR && cl < K2) {
+                            const int o_ep = orow / (3 * NORB), o_m = (orow / NORB) % 3, o_r = orow % NORB;
+                            dst[((o_ep * 3 + o_m) * NN + o_r * NORB) * 2 + cl] = c[v];
                         }
-                    };
-                    const f64x4 zero = {0.0, 0.0, 0.0, 0.0};
-                    auto b_of = [&](int s) { return pb[4 * s * TW]; };
-                    if (do_u) {
-                        const f64x4 cu = mma_chain<C::KA / 4>(
-                            [&](int s) { return pa1[(4 * s / K2) * C::YB + (4 * s) % K2]; }, b_of, zero);
-                        store_tile(sU, cu);
                     }
-                    if (do_t) {
-                        const f64x4 ct = mma_chain<C::KA / 4>(
-                            [&](int s) { return neg_if(pa2[(4 * s / K2) * 3 * C::YB + ((4 * s) % K2) * NORB], neg); },
-                            b_of, zero);
-                        store_tile(sT, ct);
-                    }
+                };
+                const f64x4 zero = {0.0, 0.0, 0.0, 0.0};
+                auto b_of = [&](int s) { return pb[4 * s * TW]; };
+                if (do_u) {
+                    const f64x4 cu = mma_chain<C::KA / 4>(
+                        [&](int s) { return pa1[(4 * s / K2) * C::YB + (4 * s) % K2]; }, b_of, zero);
+                    store_tile(ub, cu);
                 }
-                __syncthreads();
+                if (do_t) {
+                    const f64x4 ct = mma_chain<C::KA / 4>(
+                        [&](int s) { return neg_if(pa2[(4 * s / K2) * 3 * C::YB + ((4 * s) % K2) * NORB], neg); },
+                        b_of, zero);
+                    store_tile(tb, ct);
+                }
+            };
+            auto terms = [&](int kp) {
+                const double* ub = sU + (kp & 1) * C::L_U;
+                const double* tb = sT + (kp & 1) * C::L_U;
                 if (wave == 2 || wave == 3) {
                     // dG[ep][x][u] (+)= sum_{j,c} conj(T^H_j[ep][c][x]) A_j[c][u]: rows (ep, x)
                     if (dG) {
@@ -406,22 +413,28 @@ __global__ __launch_bounds__(512) void bwd_mfma_kernel(Dims d, const double* __r
                         int row = l16;
                         if (row >= C::GR) row = C::GR - 1;
                         const int ep = row / NORB, x = row % NORB;
-                        const double* pa = sT + (ep * 3 * NN + x) * 2 + (l4 >> 1) * 2 * NORB + (l4 & 1);
+                        const double* pa = tb + (ep * 3 * NN + x) * 2 + (l4 >> 1) * 2 * NORB + (l4 & 1);
                         const double* pb = sTA + l4 * TW + 16 * nt + l16;
                         const bool neg = (l4 & 1) != 0;
+                        // the next momentum's previous values are read before this
+                        // momentum's stores are issued: a wait for those loads then
+                        // does not also wait for the stores
+                        double gnext[4] = {0.0, 0.0, 0.0, 0.0};
+                        if (kp + 1 < NKZ) load_prev(kp + 1, gnext);
                         const f64x4 cg = mma_chain<C::KA / 4>(
                             [&](int s) { return neg_if(pa[(4 * s / K2) * 2 * NN + ((4 * s) % K2) * NORB], neg); },
                             [&](int s) { return pb[4 * s * TW]; }, f64x4{0.0, 0.0, 0.0, 0.0});
 #pragma unroll
-                        for (int v = 0; v < 4; ++v)
+                        for (int v = 0; v < 4; ++v) {
                             if (g_ok[v]) dG[g_off[v] + g_k * kp] = gprev[v] + cg[v];
-                        if (kp + 1 < NKZ) load_prev(kp + 1);
+                            gprev[v] = gnext[v];
+                        }
                     }
                 } else if (dApart && wave < 6) {
                     // dA_m[r][c] += sum_{ep,c'} U_m[ep][r][c'] conj(B_ep[c][c'])
                     //             + sum_{ep,q} T^H_m[ep][r][q] B_ep[q][c]: rows (m, r);
                     // waves 0, 1, 4, 5, so that each SIMD carries at most two of the
-                    // four tiles of this phase
+                    // four tiles of this product
                     const int w4 = (wave & 1) + 2 * (wave >> 2), mt = w4 >> 1, nt = w4 & 1;
                     int row = 16 * mt + l16;
                     if (row >= C::AR) row = C::AR - 1;
@@ -431,16 +444,21 @@ __global__ __launch_bounds__(512) void bwd_mfma_kernel(Dims d, const double* __r
                     dacc = mma_chain<C::KB / 4>(
                         [&](int s) {
                             const int t0 = 4 * s, th = t0 % (C::EP * K2);
-                            return (t0 / (C::EP * K2) ? sT : sU)[arow + (th / K2) * 6 * NN + th % K2];
+                            return (t0 / (C::EP * K2) ? tb : ub)[arow + (th / K2) * 6 * NN + th % K2];
                         },
                         [&](int s) { return pb[4 * s * TW]; }, dacc);
                 }
-                // the next momentum's Y and tables (sY, sU and sT are no longer read by
-                // this round; the other table buffer was last read a round ago), and
-                // in the last round the first W of the next energies (buffer 0, last
-                // read by the GEMM's final momentum)
-                if (kp + 1 < NKZ) stage(kp + 1);
-                else if (E0 + C::EP < E_hi) store_w(0);
+            };
+            stage_y(0);
+            __syncthreads();
+            for (int kp = 0; kp <= NKZ; ++kp) {
+                if (kp < NKZ) uv(kp);
+                if (kp > 0) terms(kp - 1);
+                if (kp + 1 < NKZ) stage_y(kp + 1);
+                if (kp < NKZ) stage_tb(kp);
+                // the first W of the next energies (buffer 0, last read by the GEMM's
+                // final momentum)
+                if (kp == NKZ && E0 + C::EP < E_hi) store_w(0);
                 __syncthreads();
             }
         }
