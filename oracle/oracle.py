@@ -248,6 +248,22 @@ def combine_d(dims, Dfull, nbr, lib=None) -> np.ndarray:
     return out
 
 
+def absorption_d(dims, Dopp) -> np.ndarray:
+    """Coefficients of the absorption branch (frequency -w) of Eq. 3's integral
+    over signed frequencies, from the combined table of the opposite component.
+
+    For real displacement fields the lesser and greater phonon Green's functions
+    are related by D<_ab(q, -w) = D>_ba(-q, w) (and with < and > exchanged).  The
+    bracket D_ba - D_bb - D_aa + D_ab of Eq. 3 is symmetric in a <-> b, so on the
+    combined per-neighbour tables the relation reads, with the Cartesian indices
+    exchanged:  Dm[q, w, a, n, i, j] = Dopp[(-q) mod Nqz, w, a, n, j, i]."""
+    _check(Dopp, dims.d_shape, np.complex128, "Dopp")
+    out = np.empty_like(Dopp)
+    for q in range(dims.nqz):
+        out[q] = np.swapaxes(Dopp[(-q) % dims.nqz], -1, -2)
+    return out
+
+
 def _check_pse_inputs(dims, Gs, Go, dH, nbr):
     _check(Gs, dims.g_shape, np.complex128, "Gs")
     _check(Go, dims.g_shape, np.complex128, "Go")
