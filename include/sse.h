@@ -68,7 +68,7 @@
 extern "C" {
 #endif
 
-#define SSE_ABI_VERSION 4
+#define SSE_ABI_VERSION 5
 
 typedef struct sse_dims {
     int64_t nkz;     /* electron momentum points kz (periodic grid)              */
@@ -251,6 +251,21 @@ int sse_backward_noalloc(const sse_dims* dims, const double* G, const double* D,
 
 /* Size in bytes of the device array behind sse_backward_noalloc. */
 size_t sse_noalloc_scratch_bytes(void);
+
+/*
+ * Coefficients of the absorption branch of Eq. 3 (the frequency -w of its
+ * integral over signed frequencies, the Dm argument of sse_forward_signed and
+ * sse_forward_ex) from the combined table of the opposite component:
+ *   Dm[q,w,a,n,i,j] = Dopp[(nqz - q) mod nqz, w, a, n, j, i].
+ * The paper gives no relation for D(-w); this one holds for real displacement
+ * fields, D<_ab(q, -w) = D>_ba(-q, w) (and with < and > exchanged), and the
+ * bracket D_ba - D_bb - D_aa + D_ab of Eq. 3 is symmetric in a <-> b.  So for
+ * Sigma< pass Dp = D< and Dm = sse_absorption_d(D>), for Sigma> Dp = D> and
+ * Dm = sse_absorption_d(D<).  Dopp and Dm are [nqz][nw][na][nb][3][3] complex;
+ * a permutation of entries, bit for bit.  Dm must not overlap Dopp
+ * (SSE_ERR_DIMS).  No workspace.
+ */
+int sse_absorption_d(const sse_dims* dims, const double* Dopp, double* Dm, void* stream);
 
 /*
  * The bracket of Eq. 3 for every neighbour slot, the step that prepares D:

@@ -12,7 +12,7 @@ SSE_OK, SSE_ERR_NULL, SSE_ERR_DIMS, SSE_ERR_WORKSPACE, SSE_ERR_PRECISION, SSE_ER
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x2": 2, "bf16x3": 3, "fp16x2": 4}
 EXPORTS = ("sse_abi_version", "sse_last_error", "sse_workspace_bytes", "sse_effective_flops",
            "sse_forward", "sse_forward_signed", "sse_forward_ex", "sse_backward", "sse_backward_signed",
-           "sse_check_nbr", "sse_combine_d", "sse_phonon_forward", "sse_backward_noalloc",
+           "sse_check_nbr", "sse_combine_d", "sse_absorption_d", "sse_phonon_forward", "sse_backward_noalloc",
            "sse_noalloc_scratch_bytes")
 
 
@@ -57,10 +57,11 @@ def load():
     lib.sse_noalloc_scratch_bytes.argtypes, lib.sse_noalloc_scratch_bytes.restype = [], SZ
     lib.sse_check_nbr.argtypes = [DP, P, P, SZ, P]
     lib.sse_combine_d.argtypes = [DP, P, P, P, P, SZ, P]
+    lib.sse_absorption_d.argtypes = [DP, P, P, P]
     lib.sse_phonon_forward.argtypes = [DP, P, P, P, P, D, D, P, P]
     for f in (lib.sse_workspace_bytes, lib.sse_effective_flops, lib.sse_forward, lib.sse_forward_signed,
               lib.sse_forward_ex, lib.sse_backward, lib.sse_backward_signed, lib.sse_check_nbr, lib.sse_combine_d,
-              lib.sse_phonon_forward, lib.sse_backward_noalloc):
+              lib.sse_absorption_d, lib.sse_phonon_forward, lib.sse_backward_noalloc):
         f.restype = ctypes.c_int
     _lib = lib
     return lib

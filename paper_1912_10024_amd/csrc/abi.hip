@@ -238,6 +238,20 @@ int sse_backward_signed(const sse_dims* dims, const double* G, const double* Dp,
                          workspace_bytes, stream, true);
 }
 
+int sse_absorption_d(const sse_dims* dims, const double* Dopp, double* Dm, void* stream) {
+    int rc = check_dims(dims);
+    if (rc) return rc;
+    if (!Dopp || !Dm) return fail(SSE_ERR_NULL, "a tensor pointer is NULL");
+    const sse::Dims d = sse::to_dims(*dims);
+    const size_t bytes = 16 * (size_t)(d.nqz * d.nw * d.na * d.nb * 9);
+    const char* in = reinterpret_cast<const char*>(Dopp);
+    const char* out = reinterpret_cast<const char*>(Dm);
+    if (in < out + bytes && out < in + bytes) return fail(SSE_ERR_DIMS, "Dm overlaps Dopp");
+    hipError_t e = sse::launch_absorption_d(d, Dopp, Dm, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "absorption_d launch");
+    return ok();
+}
+
 int sse_combine_d(const sse_dims* dims, const double* Dfull, const int32_t* nbr, double* Dc, void* workspace,
                   size_t workspace_bytes, void* stream) {
     int rc = check_dims(dims);

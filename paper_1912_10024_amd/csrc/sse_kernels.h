@@ -55,6 +55,9 @@ hipError_t launch_bwd(const Dims& d, const double* G, const double* Dp, const do
                       const int32_t* nbr, cd alpha, const double* gS, double* dG, double* dDp, double* dDm, double* dA,
                       void* ws, hipStream_t stream, bool signed_form);
 
+// absorption-branch coefficients: Dm[q,w,a,n,i,j] = Dopp[(-q) mod nqz, w, a, n, j, i]
+hipError_t launch_absorption_d(const Dims& d, const double* Dopp, double* Dm, hipStream_t stream);
+
 // Eq. 3 bracket from the full phonon blocks (symmetric neighbour table)
 size_t combine_workspace_bytes(const Dims& d);
 hipError_t launch_reverse_slots(const Dims& d, const int32_t* nbr, void* ws, hipStream_t stream);

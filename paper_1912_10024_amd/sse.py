@@ -111,6 +111,24 @@ def combine_d(Dfull: torch.Tensor, nbr: torch.Tensor) -> torch.Tensor:
     return out
 
 
+def absorption_d(Dopp: torch.Tensor) -> torch.Tensor:
+    """Coefficients at -w for the signed-frequency form (the Dm argument of
+    forward_signed / forward_ex) from the combined [nqz, nw, na, nb, 3, 3] table of
+    the opposite component: Dm[q,w,a,n,i,j] = Dopp[(-q) mod nqz, w, a, n, j, i]
+    (D<_ab(q, -w) = D>_ba(-q, w) for real displacement fields)."""
+    Dopp = _resolved(Dopp)
+    _check_tensor(Dopp, "Dopp")
+    if Dopp.dim() != 6 or Dopp.shape[4:] != (3, 3):
+        raise ValueError("Dopp must be [nqz, nw, na, nb, 3, 3]")
+    nqz, nw, na, nb = Dopp.shape[:4]
+    d = Dims(nkz=nqz, ne=1, nqz=nqz, nw=nw, na=na, nb=nb, norb=1, g_slots=1)
+    out = torch.empty_like(Dopp)
+    lib = _lib.load()
+    cd = _lib.SSEDims.of(d)
+    _raise(lib.sse_absorption_d(ctypes.byref(cd), _ptr(Dopp), _ptr(out), _stream(Dopp.device)), "sse_absorption_d")
+    return out
+
+
 def forward(G, D, dH, nbr, alpha=1j, precision: str = "fp64", out=None, ws=None) -> torch.Tensor:
     """Sigma[nkz, ne, na, norb, norb] = Eq. 3 (one of lesser/greater)."""
     return _forward(G, D, D, dH, None, nbr, alpha, precision, out, ws)
