@@ -39,8 +39,9 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--config", default="device", choices=["tiny", "mid", "device"])
-    p.add_argument("--forms", default="fp64,fp32,bf16x2,fp16x2",
-                   help="comma-separated operand precisions to time; the first is the headline value")
+    p.add_argument("--forms", default="fp64,fp32,bf16x2,fp16x2,fp16",
+                   help="comma-separated operand precisions to time; the first is the headline value "
+                        "(fp16 and fp16_unscaled: the single-term comparison forms)")
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle baseline sample")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-phonon", action="store_true", help="skip the phonon self-energy timing")
@@ -359,18 +360,23 @@ def main():
     if not args.no_cpu:
         f_block = f_eff / (d.nkz * d.ne * d.na)
         cpu, cpu_pts, cpu_ref = cpu_baseline(d, G, D, dH, nbr, args.cpu_seconds, f_block)
-    peaks = {"fp64": FP64_MFMA_PEAK, "fp32": FP32_MFMA_PEAK, "bf16x2": FP16_MFMA_PEAK, "fp16x2": FP16_MFMA_PEAK}
+    peaks = {"fp64": FP64_MFMA_PEAK, "fp32": FP32_MFMA_PEAK, "bf16x2": FP16_MFMA_PEAK, "fp16x2": FP16_MFMA_PEAK,
+             "fp16": FP16_MFMA_PEAK, "fp16_unscaled": FP16_MFMA_PEAK}
     # fp64: the useful flops of the regrouped form (GEMM and all twelve products
     # that form P; vector ALUs and matrix cores share the fp64 peak); fp32: the
     # fp32 matrix-core work (GEMM and the nine right products); 16-bit forms: the
     # four hi/lo partial products of both on the 16-bit matrix cores
     mfma_flops = {"fp64": flops.pd_useful_flops(d), "fp32": flops.pd_mfma_flops(d),
-                  "bf16x2": flops.split16_mfma_flops(d), "fp16x2": flops.split16_mfma_flops(d)}
+                  "bf16x2": flops.split16_mfma_flops(d), "fp16x2": flops.split16_mfma_flops(d),
+                  "fp16": flops.single16_mfma_flops(d), "fp16_unscaled": flops.single16_mfma_flops(d)}
     whats = {"fp64": "useful fp64 flops: P.D GEMM + the 12 products forming P (X on the vector ALUs, X.gradH^H on "
                      "the matrix cores; one shared fp64 peak)",
              "fp32": "fp32 matrix-core flops: P.D GEMM + P = X.gradH^H products",
              "bf16x2": "16-bit matrix-core flops: 4 hi/lo products of the P.D GEMM and of P = X.gradH^H",
-             "fp16x2": "16-bit matrix-core flops: 4 hi/lo products of the P.D GEMM and of P = X.gradH^H"}
+             "fp16x2": "16-bit matrix-core flops: 4 hi/lo products of the P.D GEMM and of P = X.gradH^H",
+             "fp16": "16-bit matrix-core flops of the single-term form run on the split kernel: 2x the P.D GEMM, "
+                     "4x P = X.gradH^H (flops.single16_mfma_flops)",
+             "fp16_unscaled": "as fp16 (flops.single16_mfma_flops)"}
     traffic_records = {"fp64": ("fwd_mfma_device_traffic.txt", FWD_SOURCES),
                        "fp16x2": ("fwd_h16_device_traffic.txt", H16_SOURCES)}
     res = {}

@@ -68,7 +68,7 @@
 extern "C" {
 #endif
 
-#define SSE_ABI_VERSION 5
+#define SSE_ABI_VERSION 6
 
 typedef struct sse_dims {
     int64_t nkz;     /* electron momentum points kz (periodic grid)              */
@@ -94,13 +94,29 @@ enum sse_precision {
                         relative errors near 1e-5                                        */
     SSE_BF16X3 = 3,  /* three-term bfloat16 split (24 significant bits); declared for
                         the interface, not built: every call returns SSE_ERR_PRECISION    */
-    SSE_FP16X2 = 4   /* half precision with compensation (Sec. "Mixed-Precision
+    SSE_FP16X2 = 4,  /* half precision with compensation (Sec. "Mixed-Precision
                         Computation"): D, grad H and the left products normalised
                         by powers of two (per atom; per K chunk and source energy),
                         every operand of the dense product split into fp16 hi + lo,
                         the four partial products on the fp16 matrix cores, each K
                         chunk accumulated in fp32, unscaled and added in fp64; fp64
                         gather and (qz, w, +/-) reduction                           */
+    SSE_FP16 = 5,    /* the paper's half-precision scheme as it describes it (Sec.
+                        "Mixed-Precision Computation"): the normalisation of
+                        SSE_FP16X2 with one fp16 term per operand (no lo parts),
+                        fp32 accumulation per K chunk, fp64 reduction.  11
+                        significant bits per operand: expect relative errors near
+                        1e-4.  A comparison form: it runs the SSE_FP16X2 kernel with
+                        the lo terms dropped, not a kernel tuned for one term.  One
+                        coefficient table only (sse_forward, or the other entry
+                        points with Dm == Dp), on the matrix-core shapes; otherwise
+                        SSE_ERR_PRECISION                                           */
+    SSE_FP16_UNSCALED = 6 /* SSE_FP16 without the power-of-two factors: every operand
+                        rounded to fp16 as it is, magnitudes beyond the fp16 range
+                        clamped to 65504, values below it kept as fp16 subnormals
+                        or zero.  The paper's comparison for its normalisation
+                        (Sec. "Mixed-Precision Convergence"); same limits as
+                        SSE_FP16                                                    */
 };
 
 enum sse_status {

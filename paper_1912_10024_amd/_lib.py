@@ -8,8 +8,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsse.so")
 
 SSE_OK, SSE_ERR_NULL, SSE_ERR_DIMS, SSE_ERR_WORKSPACE, SSE_ERR_PRECISION, SSE_ERR_HIP, SSE_ERR_NBR = range(7)
-# the sse_precision codes of include/sse.h ("bf16x3" is declared there but not built)
-PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x2": 2, "bf16x3": 3, "fp16x2": 4}
+# the sse_precision codes of include/sse.h ("bf16x3" is declared there but not built;
+# "fp16" and "fp16_unscaled" are the single-term comparison forms, one table only)
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x2": 2, "bf16x3": 3, "fp16x2": 4, "fp16": 5, "fp16_unscaled": 6}
 EXPORTS = ("sse_abi_version", "sse_last_error", "sse_workspace_bytes", "sse_effective_flops",
            "sse_forward", "sse_forward_signed", "sse_forward_ex", "sse_backward", "sse_backward_signed",
            "sse_check_nbr", "sse_combine_d", "sse_absorption_d", "sse_phonon_forward", "sse_backward_noalloc",

@@ -76,7 +76,8 @@ int hip_fail(hipError_t e, const char* what) {
 }
 
 bool precision_known(int p) {
-    return p == SSE_FP64 || p == SSE_FP32 || p == SSE_BF16X2 || p == SSE_BF16X3 || p == SSE_FP16X2;
+    return p == SSE_FP64 || p == SSE_FP32 || p == SSE_BF16X2 || p == SSE_BF16X3 || p == SSE_FP16X2 || p == SSE_FP16 ||
+           p == SSE_FP16_UNSCALED;
 }
 
 // precision check of the forward entry points: unknown codes, and the declared
@@ -142,6 +143,9 @@ int forward_impl(const sse_dims* dims, const double* G, const double* Dp, const 
     if (rc) return rc;
     if (!G || !Dp || !Dm || !dH || !nbr || !Sigma) return fail(SSE_ERR_NULL, "a tensor pointer is NULL");
     if ((rc = check_precision(precision))) return rc;
+    if ((precision == SSE_FP16 || precision == SSE_FP16_UNSCALED) && Dm != Dp)
+        return fail(SSE_ERR_PRECISION, "precision %d (single-term fp16) is built for one coefficient table (Dm == Dp) only",
+                    precision);
     size_t need = 0;
     sse_workspace_bytes(dims, precision, 0, &need);
     if (need > 0 && (workspace == nullptr || workspace_bytes < need))

@@ -61,10 +61,14 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
+// Operand arithmetic per precision: the 16-bit matrix instruction, the split
+// of an fp32 value into its (hi, lo) word, whether the lo terms are kept (LO)
+// and whether the operands are normalised by powers of two (NORM)
 template <int PREC>
 struct Split16;
 template <>
 struct Split16<SSE_FP16X2> {
+    static constexpr bool LO = true, NORM = true;
     static __device__ __forceinline__ f32x4 mma(u32x4 a, u32x4 b, f32x4 c) {
         return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0, 0,
                                                       0);
@@ -78,6 +82,7 @@ struct Split16<SSE_FP16X2> {
 };
 template <>
 struct Split16<SSE_BF16X2> {
+    static constexpr bool LO = true, NORM = false;
     static __device__ __forceinline__ f32x4 mma(u32x4 a, u32x4 b, f32x4 c) {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
                                                        0, 0);
@@ -86,6 +91,31 @@ struct Split16<SSE_BF16X2> {
         const __bf16 h = (__bf16)x;  // round to nearest even
         const __bf16 l = (__bf16)(x - (float)h);
         return (unsigned)__builtin_bit_cast(unsigned short, h) | ((unsigned)__builtin_bit_cast(unsigned short, l) << 16);
+    }
+};
+// The paper's scheme without compensation: one fp16 term per operand (lo = 0,
+// so the P tiles' lo products add zeros and the main GEMM drops its lo
+// instruction), after the normalisation of the two-term form
+template <>
+struct Split16<SSE_FP16> {
+    static constexpr bool LO = false, NORM = true;
+    static __device__ __forceinline__ f32x4 mma(u32x4 a, u32x4 b, f32x4 c) {
+        return Split16<SSE_FP16X2>::mma(a, b, c);
+    }
+    static __device__ __forceinline__ unsigned split(float x) {
+        return (unsigned)__builtin_bit_cast(unsigned short, (_Float16)x);
+    }
+};
+// ... and without the normalisation: magnitudes beyond the fp16 range are
+// clamped to its largest finite value, smaller ones round to fp16 as they are
+template <>
+struct Split16<SSE_FP16_UNSCALED> {
+    static constexpr bool LO = false, NORM = false;
+    static __device__ __forceinline__ f32x4 mma(u32x4 a, u32x4 b, f32x4 c) {
+        return Split16<SSE_FP16X2>::mma(a, b, c);
+    }
+    static __device__ __forceinline__ unsigned split(float x) {
+        return Split16<SSE_FP16>::split(fminf(fmaxf(x, -65504.0f), 65504.0f));
     }
 };
 
@@ -192,7 +222,7 @@ __global__ __launch_bounds__(512) void fwd_h16_kernel(Dims d, const double* __re
                                                       cd alpha, double* __restrict__ S) {
     using C = H16Cfg<NORB, NKZ, NW, NB, EB>;
     using O = Split16<PREC>;
-    constexpr bool NORM = PREC == SSE_FP16X2;
+    constexpr bool NORM = O::NORM;
     extern __shared__ double lds[];
     uint4* sD = reinterpret_cast<uint4*>(lds);
     uint4* sP = sD + C::L_D;
@@ -475,12 +505,14 @@ __global__ __launch_bounds__(512) void fwd_h16_kernel(Dims d, const double* __re
 #pragma unroll
                 for (int nt = 0; nt < C::NT; ++nt)
                     part[nt] = O::mma(ah, as_u32x4(bv[cur][nt]), t == 0 ? zero_acc : part[nt]);
+                if constexpr (O::LO) {
 #pragma unroll
-                for (int nt = 0; nt < C::NT; ++nt) part[nt] = O::mma(al, as_u32x4(bv[cur][nt]), part[nt]);
+                    for (int nt = 0; nt < C::NT; ++nt) part[nt] = O::mma(al, as_u32x4(bv[cur][nt]), part[nt]);
+                }
             }
             if (has_extra) {
                 part_x = O::mma(hi_operand(ax[cur]), as_u32x4(bx[cur]), t == 0 ? zero_acc : part_x);
-                part_x = O::mma(lo_operand(ax[cur]), as_u32x4(bx[cur]), part_x);
+                if constexpr (O::LO) part_x = O::mma(lo_operand(ax[cur]), as_u32x4(bx[cur]), part_x);
             }
         }
         // the chunk (one qz per output momentum) goes into the fp64 sums; fp16:
@@ -633,10 +665,12 @@ static hipError_t launch_h16(const Dims& d, const double* G, const double* D, co
                              const int32_t* nbr, cd alpha, double* S, hipStream_t stream, int flags) {
     constexpr int kBoth = kBranchMinus | kBranchPlus, kPlusAdd = kBranchPlus | kAccumulate;
     if (flags == kBoth) return launch_h16_flags<NORB, NKZ, NW, NB, PREC, kBoth>(d, G, D, A, B, nbr, alpha, S, stream);
-    if (flags == kBranchMinus)
-        return launch_h16_flags<NORB, NKZ, NW, NB, PREC, kBranchMinus>(d, G, D, A, B, nbr, alpha, S, stream);
-    if (flags == kPlusAdd)
-        return launch_h16_flags<NORB, NKZ, NW, NB, PREC, kPlusAdd>(d, G, D, A, B, nbr, alpha, S, stream);
+    if constexpr (Split16<PREC>::LO) {  // the single-term forms take one table only
+        if (flags == kBranchMinus)
+            return launch_h16_flags<NORB, NKZ, NW, NB, PREC, kBranchMinus>(d, G, D, A, B, nbr, alpha, S, stream);
+        if (flags == kPlusAdd)
+            return launch_h16_flags<NORB, NKZ, NW, NB, PREC, kPlusAdd>(d, G, D, A, B, nbr, alpha, S, stream);
+    }
     return hipErrorInvalidValue;
 }
 
@@ -656,6 +690,9 @@ hipError_t launch_fwd_h16(const Dims& d, int precision, const double* G, const d
                           const double* B, const int32_t* nbr, cd alpha, double* S, hipStream_t stream, int flags) {
     if (precision == SSE_FP16X2) return dispatch_h16<SSE_FP16X2>(d, G, D, A, B, nbr, alpha, S, stream, flags);
     if (precision == SSE_BF16X2) return dispatch_h16<SSE_BF16X2>(d, G, D, A, B, nbr, alpha, S, stream, flags);
+    if (precision == SSE_FP16) return dispatch_h16<SSE_FP16>(d, G, D, A, B, nbr, alpha, S, stream, flags);
+    if (precision == SSE_FP16_UNSCALED)
+        return dispatch_h16<SSE_FP16_UNSCALED>(d, G, D, A, B, nbr, alpha, S, stream, flags);
     return hipErrorInvalidValue;
 }
 

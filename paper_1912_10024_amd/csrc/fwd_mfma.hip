@@ -659,7 +659,7 @@ hipError_t launch_fwd_mfma(const Dims& d, int precision, const double* G, const 
                            const double* B, const int32_t* nbr, cd alpha, double* S, hipStream_t stream, int flags) {
     if (precision == SSE_FP64) return dispatch_fwd<SSE_FP64>(d, G, D, A, B, nbr, alpha, S, stream, flags);
     if (precision == SSE_FP32) return dispatch_fwd<SSE_FP32>(d, G, D, A, B, nbr, alpha, S, stream, flags);
-    if (precision == SSE_FP16X2 || precision == SSE_BF16X2)
+    if (precision == SSE_FP16X2 || precision == SSE_BF16X2 || precision == SSE_FP16 || precision == SSE_FP16_UNSCALED)
         return launch_fwd_h16(d, precision, G, D, A, B, nbr, alpha, S, stream, flags);
     return hipErrorInvalidValue;
 }

@@ -29,8 +29,9 @@ hipError_t launch_fwd_mfma(const Dims& d, int precision, const double* G, const 
                            const double* B, const int32_t* nbr, cd alpha, double* S, hipStream_t stream,
                            int flags = kBranchMinus | kBranchPlus);
 
-// matrix-core forward with split 16-bit operands (SSE_FP16X2, SSE_BF16X2) for
-// the shapes of fwd_mfma_specialised; B and flags as for launch_fwd_mfma
+// matrix-core forward with split 16-bit operands (SSE_FP16X2, SSE_BF16X2, and the
+// single-term SSE_FP16 and SSE_FP16_UNSCALED with the flags of the one-table form
+// only) for the shapes of fwd_mfma_specialised; B and flags as for launch_fwd_mfma
 hipError_t launch_fwd_h16(const Dims& d, int precision, const double* G, const double* D, const double* A,
                           const double* B, const int32_t* nbr, cd alpha, double* S, hipStream_t stream, int flags);
 

@@ -67,6 +67,15 @@ def split16_mfma_flops(d) -> float:
     return 4.0 * pd_mfma_flops(d)
 
 
+def single16_mfma_flops(d) -> float:
+    """Flops the single-term fp16 forms issue on the 16-bit matrix cores: they run
+    the split kernel with the lo terms zero, so the P tiles issue the four partial
+    products of the split forms and the P.D GEMM keeps one of its two
+    instructions (hi parts of D against the (hi, lo) pairs of P: twice the GEMM's
+    useful flops)."""
+    return 2.0 * pd_gemm_flops(d) + 4.0 * (pd_mfma_flops(d) - pd_gemm_flops(d))
+
+
 def pd_stencil_flops(d) -> float:
     """Real adds of the (w, +/-) energy stencil: 2 complex adds per valid (k, E, w, s, r, c)."""
     valid = 0

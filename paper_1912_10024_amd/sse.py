@@ -130,7 +130,9 @@ def absorption_d(Dopp: torch.Tensor) -> torch.Tensor:
 
 
 def forward(G, D, dH, nbr, alpha=1j, precision: str = "fp64", out=None, ws=None) -> torch.Tensor:
-    """Sigma[nkz, ne, na, norb, norb] = Eq. 3 (one of lesser/greater)."""
+    """Sigma[nkz, ne, na, norb, norb] = Eq. 3 (one of lesser/greater).  precision
+    is a key of PRECISIONS (the sse_precision codes: fp64, fp32, bf16x2, fp16x2,
+    and the single-term comparison forms fp16 and fp16_unscaled)."""
     return _forward(G, D, D, dH, None, nbr, alpha, precision, out, ws)
 
 

@@ -75,13 +75,29 @@ def test_bad_precision_rejected(lib):
 
 def test_precision_codes_match_the_interface():
     """The header's sse_precision codes are the interface's (FP64 0, FP32 1,
-    BF16X2 2, BF16X3 3) plus FP16X2 4, and the binding uses the same codes."""
+    BF16X2 2, BF16X3 3) plus FP16X2 4 and the single-term comparison forms FP16 5
+    and FP16_UNSCALED 6, and the binding uses the same codes."""
     txt = open(os.path.join(ROOT, "include", "sse.h")).read()
     enum = txt[txt.index("enum sse_precision"):txt.index("};", txt.index("enum sse_precision"))]
     enum = re.sub(r"/\*.*?\*/", "", enum, flags=re.S)
     codes = {m.group(1).lower(): int(m.group(2)) for m in re.finditer(r"SSE_(\w+)\s*=\s*(\d+)", enum)}
-    assert codes == {"fp64": 0, "fp32": 1, "bf16x2": 2, "bf16x3": 3, "fp16x2": 4}
+    assert codes == {"fp64": 0, "fp32": 1, "bf16x2": 2, "bf16x3": 3, "fp16x2": 4, "fp16": 5, "fp16_unscaled": 6}
     assert codes == _lib.PRECISIONS
+
+
+@pytest.mark.parametrize("name", ["fp16", "fp16_unscaled"])
+def test_single_term_forms_refuse_two_tables(lib, name):
+    """The single-term fp16 forms take one coefficient table: a signed call with
+    Dm != Dp is a precision error before any launch (the pointers here are never
+    dereferenced), while Dm == Dp passes the precision check and stops at the
+    workspace check (no workspace given)."""
+    cd = _lib.SSEDims.of(CONFIGS["mid"])
+    P = ctypes.c_void_p
+    prec = _lib.PRECISIONS[name]
+    args = lambda dm: (ctypes.byref(cd), P(8), P(16), P(dm), P(32), P(64), 0.0, 1.0, prec, P(128))
+    assert lib.sse_forward_signed(*args(24), None, 0, None) == _lib.SSE_ERR_PRECISION
+    assert "one coefficient table" in lib.sse_last_error().decode()
+    assert lib.sse_forward_signed(*args(16), None, 0, None) == _lib.SSE_ERR_WORKSPACE
 
 
 def test_declared_but_unbuilt_precision_is_rejected(lib):
