@@ -219,12 +219,17 @@ int sse_forward_ex(const sse_dims* dims, const double* G, const double* Dp, cons
  * (sse_workspace_bytes(dims, 0, 1) bytes suffice for every call) holds the
  * reverse neighbour adjacency (4 * (3 na + 1 + na * nb) bytes, rounded up to
  * 256) and, if ddH is wanted, S shares of every edge's dL/d(dH)
- * (16 * S * na * nb * 3 * norb^2 bytes), added in share order, so results are
- * bitwise reproducible: S = ceil(ne / 32) (one per range of 32 energies) on the
- * matrix-core shape (norb = 10, nkz = nqz = 7, nw = 10), S = nkz (one per
- * momentum) otherwise and in sse_backward_signed.  A smaller workspace than
- * this call uses is refused with SSE_ERR_WORKSPACE.  An entry of nbr outside
- * [0, na) has no terms: its ddH block is zero.
+ * (16 * S * na * nb * 3 * norb^2 bytes, rounded up to 256), added in share
+ * order, so results are bitwise reproducible: S = ceil(ne / 32) (one per range
+ * of 32 energies) on the matrix-core shape (norb = 10, nkz = nqz = 7, nw = 10),
+ * S = nkz (one per momentum) otherwise and in sse_backward_signed.  If dD is
+ * wanted on the shapes of the matrix-core phonon kernel (norb = 10, nkz = nqz
+ * = 7, nw = 10, nb = 4 or 3), it also holds a copy of dSigma with the atom
+ * axis first (16 * na * nkz * ne * norb^2 bytes, the size of dSigma), from
+ * which the dD kernel reads its shifted blocks (the same sums in the same
+ * order as from dSigma itself).  A smaller workspace than this call uses is
+ * refused with SSE_ERR_WORKSPACE.  An entry of nbr outside [0, na) has no
+ * terms: its ddH block is zero.
  */
 int sse_backward(const sse_dims* dims, const double* G, const double* D, const double* dH,
                  const int32_t* nbr, double alpha_re, double alpha_im, const double* dSigma,
@@ -246,7 +251,7 @@ int sse_backward_signed(const sse_dims* dims, const double* G, const double* Dp,
 /*
  * sse_backward for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
- * same kernels and results, with the workspace in a device array that is part
+ * same results bit for bit, with the workspace in a device array that is part
  * of the library (sse_noalloc_scratch_bytes() bytes, 64 MiB, held by every GPU
  * the library runs on until the process ends) instead of a caller-provided
  * buffer.  Calls no hipMalloc, hipFree or allocating routine.  Dims whose
@@ -256,7 +261,8 @@ int sse_backward_signed(const sse_dims* dims, const double* G, const double* Dp,
  * shares 16 * S * Na * Nb * 3 * Norb^2 more, S = ceil(NE / 32)
  * on the matrix-core shape (Norb = 10, Nkz = Nqz = 7, Nw = 10), S = Nkz otherwise
  * (at Nkz = 7, Norb = 10, Nb = 4, NE <= 224: about 500 atoms with ddH, about
- * 2.4 million without it).  Every call on one GPU uses that GPU's
+ * 2.4 million without it).  dD reads dSigma in place (no atom-major copy:
+ * slower than sse_backward's, the same sums).  Every call on one GPU uses that GPU's
  * array (the current device's): calls that overlap on one GPU race.  The
  * kernels rewrite every part of the array they read, so no clearing is needed
  * between calls.  Other arguments and errors as for sse_backward.

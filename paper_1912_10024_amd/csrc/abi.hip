@@ -206,32 +206,41 @@ namespace {
 int backward_impl(const sse_dims* dims, const double* G, const double* Dp, const double* Dm, const double* dH,
                   const int32_t* nbr, double alpha_re, double alpha_im, const double* dSigma, double* dG,
                   double* dDp, double* dDm, double* ddH, void* workspace, size_t workspace_bytes, void* stream,
-                  bool signed_form) {
+                  bool signed_form, bool copy_g) {
     int rc = check_dims(dims);
     if (rc) return rc;
     if (!G || !Dp || !Dm || !dH || !nbr || !dSigma) return fail(SSE_ERR_NULL, "an input pointer is NULL");
     const sse::Dims d = sse::to_dims(*dims);
     if (!sse::bwd_supported(d)) return fail(SSE_ERR_DIMS, "no adjoint kernel for these dims");
     // what this call uses (sse_workspace_bytes covers every gradient of either form)
-    const size_t need = sse::bwd_workspace_bytes_for(d, signed_form, ddH != nullptr);
+    const size_t need = sse::bwd_workspace_bytes_for(d, signed_form, ddH != nullptr, dDp || dDm, copy_g);
     if (workspace == nullptr || workspace_bytes < need)
         return fail(SSE_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace_bytes);
     if (!dG && !dDp && !dDm && !ddH) return ok();
     hipError_t e = sse::launch_bwd(d, G, Dp, Dm, dH, nbr, sse::cd{alpha_re, alpha_im}, dSigma, dG, dDp, dDm, ddH,
-                                   workspace, reinterpret_cast<hipStream_t>(stream), signed_form);
+                                   workspace, reinterpret_cast<hipStream_t>(stream), signed_form, copy_g);
     if (e != hipSuccess) return hip_fail(e, "backward launch");
     return ok();
 }
 
 }  // namespace
 
+namespace sse {
+int backward_one_table(const sse_dims* dims, const double* G, const double* D, const double* dH, const int32_t* nbr,
+                       double alpha_re, double alpha_im, const double* dSigma, double* dG, double* dD, double* ddH,
+                       void* workspace, size_t workspace_bytes, void* stream, bool copy_g) {
+    return backward_impl(dims, G, D, D, dH, nbr, alpha_re, alpha_im, dSigma, dG, dD, nullptr, ddH, workspace,
+                         workspace_bytes, stream, false, copy_g);
+}
+}  // namespace sse
+
 extern "C" {
 
 int sse_backward(const sse_dims* dims, const double* G, const double* D, const double* dH, const int32_t* nbr,
                  double alpha_re, double alpha_im, const double* dSigma, double* dG, double* dD, double* ddH,
                  void* workspace, size_t workspace_bytes, void* stream) {
-    return backward_impl(dims, G, D, D, dH, nbr, alpha_re, alpha_im, dSigma, dG, dD, nullptr, ddH, workspace,
-                         workspace_bytes, stream, false);
+    return sse::backward_one_table(dims, G, D, dH, nbr, alpha_re, alpha_im, dSigma, dG, dD, ddH, workspace,
+                                   workspace_bytes, stream, true);
 }
 
 int sse_backward_signed(const sse_dims* dims, const double* G, const double* Dp, const double* Dm, const double* dH,
@@ -239,7 +248,7 @@ int sse_backward_signed(const sse_dims* dims, const double* G, const double* Dp,
                         double* dDp, double* dDm, double* ddH, void* workspace, size_t workspace_bytes,
                         void* stream) {
     return backward_impl(dims, G, Dp, Dm, dH, nbr, alpha_re, alpha_im, dSigma, dG, dDp, dDm, ddH, workspace,
-                         workspace_bytes, stream, true);
+                         workspace_bytes, stream, true, true);
 }
 
 int sse_absorption_d(const sse_dims* dims, const double* Dopp, double* Dm, void* stream) {

@@ -96,7 +96,9 @@ __global__ void zero_i32_kernel(int64_t n, int32_t* p) {
 
 // ws layout after the reverse adjacency (256-byte aligned): the d gradH sums of
 // every edge, one set per momentum k' (complex [nkz][na*nb][3][norb][norb]),
-// added in k' order by bwd_dh_reduce_kernel
+// added in k' order by bwd_dh_reduce_kernel (one per range of energies on the
+// matrix cores), if d gradH is asked for; then the atom-major copy of g that
+// the matrix-core D gradient reads, if dD is asked for with copy_g
 static size_t bwd_csr_bytes(const Dims& d) {
     return (sizeof(int32_t) * (size_t)(3 * d.na + 1 + d.na * d.nb) + 255) / 256 * 256;
 }
@@ -108,12 +110,15 @@ static bool bwd_use_mfma(const Dims& d, bool signed_form) {
 static int64_t bwd_shares(const Dims& d, bool signed_form) {
     return bwd_use_mfma(d, signed_form) ? bwd_mfma_shares(d) : d.nkz;
 }
-size_t bwd_workspace_bytes_for(const Dims& d, bool signed_form, bool with_dh) {
-    return bwd_csr_bytes(d) +
-           (with_dh ? sizeof(cd) * (size_t)(bwd_shares(d, signed_form) * d.na * d.nb * 3 * d.norb * d.norb) : 0);
+static size_t bwd_dh_bytes(const Dims& d, bool signed_form) {
+    return (sizeof(cd) * (size_t)(bwd_shares(d, signed_form) * d.na * d.nb * 3 * d.norb * d.norb) + 255) / 256 * 256;
+}
+size_t bwd_workspace_bytes_for(const Dims& d, bool signed_form, bool with_dh, bool with_dd, bool copy_g) {
+    return bwd_csr_bytes(d) + (with_dh ? bwd_dh_bytes(d, signed_form) : 0) +
+           (with_dd && copy_g ? pse_atom_major_bytes(d) : 0);
 }
 size_t bwd_workspace_bytes(const Dims& d) {
-    return std::max(bwd_workspace_bytes_for(d, false, true), bwd_workspace_bytes_for(d, true, true));
+    return std::max(bwd_workspace_bytes_for(d, false, true, true, true), bwd_workspace_bytes_for(d, true, true, true, true));
 }
 
 // --------------------------------------------------------------- W and Y of one source point
@@ -423,10 +428,10 @@ bool bwd_supported(const Dims& d) {
            bwd_lds_dd(d) <= 160 * 1024 && d.na * d.nb <= INT32_MAX && (d.na + 7) / 8 * 8 * d.nkz <= INT32_MAX;
 }
 
-// dD (or dDp / dDm) for the given energy branches
+// dD (or dDp / dDm) for the given energy branches (gT: the atom-major copy of gS, or NULL)
 static hipError_t launch_dd(const Dims& d, const double* G, const double* A, const int32_t* nbr, const double* gS,
-                            cd calpha, double* dD, int branches, hipStream_t stream) {
-    if (pse_mfma_specialised(d)) return launch_dd_mfma(d, G, A, nbr, gS, calpha, dD, stream, branches);
+                            const double* gT, cd calpha, double* dD, int branches, hipStream_t stream) {
+    if (pse_mfma_specialised(d)) return launch_dd_mfma(d, G, A, nbr, gS, gT, calpha, dD, stream, branches);
     const size_t lds = bwd_lds_dd(d);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(bwd_dd_kernel),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -438,7 +443,7 @@ static hipError_t launch_dd(const Dims& d, const double* G, const double* A, con
 
 hipError_t launch_bwd(const Dims& d, const double* G, const double* Dp, const double* Dm, const double* A,
                       const int32_t* nbr, cd alpha, const double* gS, double* dG, double* dDp, double* dDm, double* dA,
-                      void* ws, hipStream_t stream, bool signed_form) {
+                      void* ws, hipStream_t stream, bool signed_form, bool copy_g) {
     const cd calpha{alpha.re, -alpha.im};
     const bool mfma = bwd_use_mfma(d, signed_form);
     // every attribute is set before the first launch, so a failure leaves all outputs untouched
@@ -487,12 +492,21 @@ hipError_t launch_bwd(const Dims& d, const double* G, const double* Dp, const do
             if (e != hipSuccess) return e;
         }
     }
-    if (!signed_form) return dDp ? launch_dd(d, G, A, nbr, gS, calpha, dDp, 3, stream) : hipGetLastError();
-    if (dDp) {
-        hipError_t e = launch_dd(d, G, A, nbr, gS, calpha, dDp, 1, stream);
+    if (signed_form ? !dDp && !dDm : !dDp) return hipGetLastError();
+    // the matrix-core D gradient reads g from its atom-major copy when the workspace holds one
+    double* gT = nullptr;
+    if (copy_g && pse_atom_major_bytes(d) > 0) {
+        gT = reinterpret_cast<double*>(reinterpret_cast<char*>(ws) + bwd_csr_bytes(d) +
+                                       (dA ? bwd_dh_bytes(d, signed_form) : 0));
+        hipError_t e = pse_atom_major_g(d, gS, gT, stream);
         if (e != hipSuccess) return e;
     }
-    if (dDm) return launch_dd(d, G, A, nbr, gS, calpha, dDm, 2, stream);
+    if (!signed_form) return launch_dd(d, G, A, nbr, gS, gT, calpha, dDp, 3, stream);
+    if (dDp) {
+        hipError_t e = launch_dd(d, G, A, nbr, gS, gT, calpha, dDp, 1, stream);
+        if (e != hipSuccess) return e;
+    }
+    if (dDm) return launch_dd(d, G, A, nbr, gS, gT, calpha, dDm, 2, stream);
     return hipGetLastError();
 }
 

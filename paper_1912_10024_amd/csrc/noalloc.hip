@@ -63,7 +63,9 @@ int sse_backward_noalloc(const sse_dims* dims, const double* G, const double* D,
     void* ws = nullptr;
     hipError_t e = scratch_address(&ws);
     if (e != hipSuccess) return sse::set_error(SSE_ERR_HIP, "sse_backward_noalloc: scratch address: %s", hipGetErrorString(e));
-    return sse_backward(dims, G, D, dH, nbr, alpha_re, alpha_im, dSigma, dG, dD, ddH, ws, kScratchBytes, stream);
+    // the D gradient reads g in the caller's layout: its atom-major copy would not fit the array
+    return sse::backward_one_table(dims, G, D, dH, nbr, alpha_re, alpha_im, dSigma, dG, dD, ddH, ws, kScratchBytes,
+                                   stream, false);
 }
 
 }  // extern "C"

@@ -126,13 +126,19 @@ __device__ __forceinline__ void pse_sum_row_tile(const Dims& d, const double* re
 // S: bit 0 the branch s = +1 (g at E' + w: the terms whose G sits at E - w,
 // i.e. the coefficients at +w), bit 1 the branch s = -1 (coefficients at -w);
 // the one-table form of Eq. 3 takes both.
-template <int N, int NK, int NW, int NB, int MODE>
+// AM (adjoint only): g is read from its atom-major copy (pse_atom_major_g):
+// the GEMM rows of one workgroup then come from one contiguous region of the
+// atom (a few pages) instead of one (k, E) slab per block, 147 of them for the
+// 21 energies x 7 momenta a workgroup reads at a time.  Same arithmetic in the
+// same order as AM = false.
+template <int N, int NK, int NW, int NB, int MODE, bool AM>
 __global__ __launch_bounds__(64 * (8 + NB)) void pse_mfma_kernel(
     Dims d, const double* __restrict__ Gs, const double* __restrict__ Go, const double* __restrict__ Ag,
     const int32_t* __restrict__ nbr, cd beta, double* __restrict__ Pi) {
     using C = PseCfg<N, NK, NW, NB>;
     static_assert(C::THREADS == 64 * (8 + NB), "launch bounds");
     constexpr bool ADJ = MODE != 0, UP = !ADJ || (MODE & 1) != 0, LO = ADJ && (MODE & 2) != 0;
+    static_assert(!AM || ADJ, "the atom-major copy is the adjoint's");
     constexpr int NN = C::NN;
     extern __shared__ __align__(16) double smem[];
     double* sA = smem;           // [NB][3][N][N] complex
@@ -147,9 +153,10 @@ __global__ __launch_bounds__(64 * (8 + NB)) void pse_mfma_kernel(
     const int64_t slot = 2 * d.gs * NN;   // doubles between atoms at one (k, E)
     const int64_t e_step = slot * NA;      // doubles between energies
     const int64_t k_step = e_step * NE;    // doubles between momenta
-    // the shifted operand: Gs (laid out like G) or, for the adjoint, g (one block per atom)
-    const int64_t rs_slot = ADJ ? 2 * NN : slot;
-    const int64_t rs_e = rs_slot * NA, rs_k = rs_e * NE;
+    // the shifted operand: Gs (laid out like G) or, for the adjoint, g (one block per
+    // atom), in its own layout or atom-major ([a][k][E] blocks)
+    const int64_t rs_slot = ADJ ? (AM ? 2 * NN * NE * (int64_t)NK : 2 * NN) : slot;
+    const int64_t rs_e = AM ? 2 * NN : rs_slot * NA, rs_k = AM ? 2 * NN * (int64_t)NE : rs_e * NE;
     const int nsrc = NK * NE;
 
     for (int x = tid; x < NB * 3 * NN; x += C::THREADS) {
@@ -478,11 +485,11 @@ bool pse_mfma_specialised(const Dims& d) {
     return d.norb == 10 && d.nkz == 7 && d.nqz == 7 && d.nw == 10 && (d.nb == 4 || d.nb == 3) && d.ne < (1 << 28);
 }
 
-template <int NB, int MODE>
+template <int NB, int MODE, bool AM = false>
 static hipError_t launch_pse_mfma(const Dims& d, const double* Rs, const double* Go, const double* A,
                                   const int32_t* nbr, cd beta, double* out, hipStream_t stream) {
     using C = PseCfg<10, 7, 10, NB>;
-    auto kern = pse_mfma_kernel<10, 7, 10, NB, MODE>;
+    auto kern = pse_mfma_kernel<10, 7, 10, NB, MODE, AM>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)C::LDS_BYTES);
     if (e != hipSuccess) return e;
@@ -497,8 +504,8 @@ bool pse_generic_supported(const Dims& d) {
 hipError_t launch_pse(const Dims& d, const double* Gs, const double* Go, const double* A, const int32_t* nbr, cd beta,
                       double* Pi, hipStream_t stream) {
     if (pse_mfma_specialised(d))
-        return d.nb == 4 ? launch_pse_mfma<4, 0>(d, Gs, Go, A, nbr, beta, Pi, stream)
-                         : launch_pse_mfma<3, 0>(d, Gs, Go, A, nbr, beta, Pi, stream);
+        return d.nb == 4 ? launch_pse_mfma<4, 0, false>(d, Gs, Go, A, nbr, beta, Pi, stream)
+                         : launch_pse_mfma<3, 0, false>(d, Gs, Go, A, nbr, beta, Pi, stream);
     const size_t lds = pse_generic_lds(d);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(pse_generic_kernel),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -508,19 +515,51 @@ hipError_t launch_pse(const Dims& d, const double* Gs, const double* Go, const d
     return hipGetLastError();
 }
 
-template <int MODE>
+template <int MODE, bool AM>
 static hipError_t launch_dd_mode(const Dims& d, const double* G, const double* A, const int32_t* nbr, const double* gS,
                                  cd calpha, double* dD, hipStream_t stream) {
-    return d.nb == 4 ? launch_pse_mfma<4, MODE>(d, gS, G, A, nbr, calpha, dD, stream)
-                     : launch_pse_mfma<3, MODE>(d, gS, G, A, nbr, calpha, dD, stream);
+    return d.nb == 4 ? launch_pse_mfma<4, MODE, AM>(d, gS, G, A, nbr, calpha, dD, stream)
+                     : launch_pse_mfma<3, MODE, AM>(d, gS, G, A, nbr, calpha, dD, stream);
+}
+
+template <bool AM>
+static hipError_t launch_dd_layout(const Dims& d, const double* G, const double* A, const int32_t* nbr,
+                                   const double* g, cd calpha, double* dD, hipStream_t stream, int branches) {
+    if (branches == 3) return launch_dd_mode<3, AM>(d, G, A, nbr, g, calpha, dD, stream);
+    if (branches == 1) return launch_dd_mode<1, AM>(d, G, A, nbr, g, calpha, dD, stream);
+    if (branches == 2) return launch_dd_mode<2, AM>(d, G, A, nbr, g, calpha, dD, stream);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_dd_mfma(const Dims& d, const double* G, const double* A, const int32_t* nbr, const double* gS,
-                          cd calpha, double* dD, hipStream_t stream, int branches) {
-    if (branches == 3) return launch_dd_mode<3>(d, G, A, nbr, gS, calpha, dD, stream);
-    if (branches == 1) return launch_dd_mode<1>(d, G, A, nbr, gS, calpha, dD, stream);
-    if (branches == 2) return launch_dd_mode<2>(d, G, A, nbr, gS, calpha, dD, stream);
-    return hipErrorInvalidValue;
+                          const double* gT, cd calpha, double* dD, hipStream_t stream, int branches) {
+    return gT ? launch_dd_layout<true>(d, G, A, nbr, gT, calpha, dD, stream, branches)
+              : launch_dd_layout<false>(d, G, A, nbr, gS, calpha, dD, stream, branches);
+}
+
+// ------------------------------------------------------------------ atom-major copy of g
+// gT[a][k][e][NN] (complex) = g[k][e][a][NN]: every entry written on every call
+__global__ void pse_atom_major_kernel(int64_t nkz, int64_t ne, int64_t na, int64_t nn, const double2* __restrict__ g,
+                                      double2* __restrict__ gT) {
+    const int64_t per_atom = nkz * ne * nn, total = na * per_atom;
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = x / per_atom, r = x % per_atom, blk = r / nn, rc = r % nn;
+        gT[x] = g[(blk * na + a) * nn + rc];
+    }
+}
+
+bool pse_atom_major_ok(const Dims& d) { return pse_mfma_specialised(d); }
+
+size_t pse_atom_major_bytes(const Dims& d) {
+    return pse_atom_major_ok(d) ? (size_t)(16 * d.norb * d.norb * d.nkz * d.ne * d.na + 255) / 256 * 256 : 0;
+}
+
+hipError_t pse_atom_major_g(const Dims& d, const double* g, double* gT, hipStream_t stream) {
+    const int64_t n = d.na * d.nkz * d.ne * d.norb * d.norb;
+    const unsigned grid = (unsigned)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+    hipLaunchKernelGGL(pse_atom_major_kernel, dim3(grid), dim3(256), 0, stream, d.nkz, d.ne, d.na, d.norb * d.norb,
+                       reinterpret_cast<const double2*>(g), reinterpret_cast<double2*>(gT));
+    return hipGetLastError();
 }
 
 }  // namespace sse

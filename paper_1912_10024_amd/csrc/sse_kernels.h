@@ -40,8 +40,11 @@ hipError_t launch_fwd_h16(const Dims& d, int precision, const double* G, const d
 // read Dm and feed dDm; otherwise Dp is the one table and dDp its gradient (Dm,
 // dDm unused).
 size_t bwd_workspace_bytes(const Dims& d);  // enough for either form, with every gradient
-// what one call uses: the reverse adjacency, plus the d gradH shares if that gradient is asked for
-size_t bwd_workspace_bytes_for(const Dims& d, bool signed_form, bool with_dh);
+// what one call uses: the reverse adjacency, plus the d gradH shares if that
+// gradient is asked for, plus the atom-major copy of g if the D gradient is
+// asked for with copy_g (on the dims that take it: pse_atom_major_ok)
+size_t bwd_workspace_bytes_for(const Dims& d, bool signed_form, bool with_dh, bool with_dd = false,
+                               bool copy_g = false);
 bool bwd_supported(const Dims& d);
 // dG and d gradH of the one-table form on the matrix cores (Norb = 10, Nkz = Nqz = 7,
 // Nw = 10): one workgroup per (neighbour atom, range of energies), one d gradH
@@ -54,7 +57,7 @@ hipError_t launch_bwd_mfma(const Dims& d, const double* G, const double* D, cons
                            hipStream_t stream);
 hipError_t launch_bwd(const Dims& d, const double* G, const double* Dp, const double* Dm, const double* A,
                       const int32_t* nbr, cd alpha, const double* gS, double* dG, double* dDp, double* dDm, double* dA,
-                      void* ws, hipStream_t stream, bool signed_form);
+                      void* ws, hipStream_t stream, bool signed_form, bool copy_g);
 
 // absorption-branch coefficients: Dm[q,w,a,n,i,j] = Dopp[(-q) mod nqz, w, a, n, j, i]
 hipError_t launch_absorption_d(const Dims& d, const double* Dopp, double* Dm, hipStream_t stream);
@@ -73,9 +76,21 @@ hipError_t launch_pse(const Dims& d, const double* Gs, const double* Go, const d
                       double* Pi, hipStream_t stream);
 // the D gradient of the adjoint on the same matrix-core kernel (shapes with
 // pse_mfma_specialised); branches: 1 the terms with G at E - w (coefficients at
-// +w), 2 those with G at E + w (at -w), 3 both (the one-table form)
+// +w), 2 those with G at E + w (at -w), 3 both (the one-table form).  gT: the
+// atom-major copy of gS written by pse_atom_major_g (read in its place), or NULL
 hipError_t launch_dd_mfma(const Dims& d, const double* G, const double* A, const int32_t* nbr, const double* gS,
-                          cd calpha, double* dD, hipStream_t stream, int branches = 3);
+                          const double* gT, cd calpha, double* dD, hipStream_t stream, int branches = 3);
+// the atom-major copy of g for the D gradient: whether these dims take it, its
+// bytes (0 when they do not), and the copy itself (every byte written)
+bool pse_atom_major_ok(const Dims& d);
+size_t pse_atom_major_bytes(const Dims& d);
+hipError_t pse_atom_major_g(const Dims& d, const double* g, double* gT, hipStream_t stream);
+
+// sse_backward with copy_g = true; false: the D gradient reads g in the caller's
+// layout and the workspace holds no copy of it (sse_backward_noalloc)
+int backward_one_table(const sse_dims* dims, const double* G, const double* D, const double* dH, const int32_t* nbr,
+                       double alpha_re, double alpha_im, const double* dSigma, double* dG, double* dD, double* ddH,
+                       void* workspace, size_t workspace_bytes, void* stream, bool copy_g);
 
 // sets the thread-local text that sse_last_error returns; returns code
 int set_error(int code, const char* fmt, ...);

@@ -1,7 +1,9 @@
 """sse_backward_noalloc (the adjoint with the library's own device array as its
 workspace) against sse_backward with a caller-provided workspace: the same
-kernels, so the gradients agree bit for bit, on two calls in a row, the second
-with a smaller input; a size beyond the array is refused before any launch."""
+arithmetic in the same order (sse_backward's D gradient reads an atom-major copy
+of dSigma, the no-alloc one dSigma itself), so the gradients agree bit for bit,
+on two calls in a row, the second with a smaller input; a size beyond the array
+is refused before any launch."""
 import ctypes
 
 import numpy as np
