@@ -226,8 +226,9 @@ int sse_forward_ex(const sse_dims* dims, const double* G, const double* Dp, cons
  * wanted on the shapes of the matrix-core phonon kernel (norb = 10, nkz = nqz
  * = 7, nw = 10, nb = 4 or 3), it also holds a copy of dSigma with the atom
  * axis first (16 * na * nkz * ne * norb^2 bytes, the size of dSigma), from
- * which the dD kernel reads its shifted blocks (the same sums in the same
- * order as from dSigma itself).  A smaller workspace than this call uses is
+ * which the dD kernel reads its shifted blocks of both energy branches (the
+ * same sums in the same order as from dSigma itself; sse_backward_signed
+ * reads one branch per launch from dSigma in place and needs no copy).  A smaller workspace than this call uses is
  * refused with SSE_ERR_WORKSPACE.  An entry of nbr outside [0, na) has no
  * terms: its ddH block is zero.
  */

@@ -114,8 +114,10 @@ static size_t bwd_dh_bytes(const Dims& d, bool signed_form) {
     return (sizeof(cd) * (size_t)(bwd_shares(d, signed_form) * d.na * d.nb * 3 * d.norb * d.norb) + 255) / 256 * 256;
 }
 size_t bwd_workspace_bytes_for(const Dims& d, bool signed_form, bool with_dh, bool with_dd, bool copy_g) {
+    // only the one-table form reads both energy branches of g per GEMM row, whose
+    // window is the one that the atom-major copy keeps within a few pages
     return bwd_csr_bytes(d) + (with_dh ? bwd_dh_bytes(d, signed_form) : 0) +
-           (with_dd && copy_g ? pse_atom_major_bytes(d) : 0);
+           (with_dd && copy_g && !signed_form ? pse_atom_major_bytes(d) : 0);
 }
 size_t bwd_workspace_bytes(const Dims& d) {
     return std::max(bwd_workspace_bytes_for(d, false, true, true, true), bwd_workspace_bytes_for(d, true, true, true, true));
@@ -495,7 +497,7 @@ hipError_t launch_bwd(const Dims& d, const double* G, const double* Dp, const do
     if (signed_form ? !dDp && !dDm : !dDp) return hipGetLastError();
     // the matrix-core D gradient reads g from its atom-major copy when the workspace holds one
     double* gT = nullptr;
-    if (copy_g && pse_atom_major_bytes(d) > 0) {
+    if (copy_g && !signed_form && pse_atom_major_bytes(d) > 0) {
         gT = reinterpret_cast<double*>(reinterpret_cast<char*>(ws) + bwd_csr_bytes(d) +
                                        (dA ? bwd_dh_bytes(d, signed_form) : 0));
         hipError_t e = pse_atom_major_g(d, gS, gT, stream);

@@ -41,8 +41,8 @@ hipError_t launch_fwd_h16(const Dims& d, int precision, const double* G, const d
 // dDm unused).
 size_t bwd_workspace_bytes(const Dims& d);  // enough for either form, with every gradient
 // what one call uses: the reverse adjacency, plus the d gradH shares if that
-// gradient is asked for, plus the atom-major copy of g if the D gradient is
-// asked for with copy_g (on the dims that take it: pse_atom_major_ok)
+// gradient is asked for, plus the atom-major copy of g if the D gradient of the
+// one-table form is asked for with copy_g (on the dims that take it: pse_atom_major_ok)
 size_t bwd_workspace_bytes_for(const Dims& d, bool signed_form, bool with_dh, bool with_dd = false,
                                bool copy_g = false);
 bool bwd_supported(const Dims& d);
