@@ -90,6 +90,32 @@ __global__ void rcsr_sort_kernel(int64_t na, const int32_t* __restrict__ offset,
     }
 }
 
+// atoms in decreasing in-degree (the matrix-core dG / d gradH kernel's dispatch
+// order: a workgroup's time grows with the in-degree of its atom, so the longest
+// start first and the shortest fill the end).  One workgroup; degrees above 255
+// share the first bucket; the order within a bucket is arbitrary, which changes
+// no result (every workgroup of that kernel owns its outputs).
+__global__ __launch_bounds__(1024) void rcsr_order_kernel(int64_t na, const int32_t* __restrict__ count,
+                                                          int32_t* __restrict__ order) {
+    __shared__ int32_t cursor[256];
+    const int tid = threadIdx.x;
+    if (tid < 256) cursor[tid] = 0;
+    __syncthreads();
+    auto bucket = [&](int64_t a) { return 255 - (count[a] < 255 ? count[a] : 255); };
+    for (int64_t a = tid; a < na; a += 1024) atomicAdd(&cursor[bucket(a)], 1);
+    __syncthreads();
+    if (tid == 0) {
+        int32_t run = 0;
+        for (int k = 0; k < 256; ++k) {
+            const int32_t c = cursor[k];
+            cursor[k] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    for (int64_t a = tid; a < na; a += 1024) order[atomicAdd(&cursor[bucket(a)], 1)] = (int32_t)a;
+}
+
 __global__ void zero_i32_kernel(int64_t n, int32_t* p) {
     for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) p[x] = 0;
 }
@@ -99,8 +125,8 @@ __global__ void zero_i32_kernel(int64_t n, int32_t* p) {
 // added in k' order by bwd_dh_reduce_kernel (one per range of energies on the
 // matrix cores), if d gradH is asked for; then the atom-major copy of g that
 // the matrix-core D gradient reads, if dD is asked for with copy_g
-static size_t bwd_csr_bytes(const Dims& d) {
-    return (sizeof(int32_t) * (size_t)(3 * d.na + 1 + d.na * d.nb) + 255) / 256 * 256;
+static size_t bwd_csr_bytes(const Dims& d) {  // count, offset, cursor, edges, order
+    return (sizeof(int32_t) * (size_t)(4 * d.na + 1 + d.na * d.nb) + 255) / 256 * 256;
 }
 // the matrix-core kernel keeps one d gradH share per range of energies instead
 static bool bwd_use_mfma(const Dims& d, bool signed_form) {
@@ -474,10 +500,12 @@ hipError_t launch_bwd(const Dims& d, const double* G, const double* Dp, const do
         hipLaunchKernelGGL(rcsr_fill_kernel, dim3(g1), dim3(256), 0, stream, d.na, d.nb, nbr, cursor, edges);
         const unsigned g2 = (unsigned)((d.na + 255) / 256 < 4096 ? (d.na + 255) / 256 : 4096);
         hipLaunchKernelGGL(rcsr_sort_kernel, dim3(g2), dim3(256), 0, stream, d.na, offset, edges);
+        int32_t* order = edges + d.na * d.nb;
+        if (mfma) hipLaunchKernelGGL(rcsr_order_kernel, dim3(1), dim3(1024), 0, stream, d.na, count, order);
         double* dApart = dA ? reinterpret_cast<double*>(reinterpret_cast<char*>(ws) + bwd_csr_bytes(d)) : nullptr;
         hipError_t e;
         if (mfma) {
-            e = launch_bwd_mfma(d, G, Dp, A, gS, calpha, offset, edges, dG, dApart, stream);
+            e = launch_bwd_mfma(d, G, Dp, A, gS, calpha, offset, edges, order, dG, dApart, stream);
         } else {
             const int64_t groups = (d.na + 7) / 8 * 8 * d.nkz;
             hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(kBwdThreads), lds, stream, d, G, Dp, Dm, A, gS,

@@ -28,7 +28,11 @@
 // adjacency).  Every dG element has one owner: the first edge writes it, the
 // later ones add to it in edge order.  d gradH of an edge gets one partial sum
 // per energy range, added in range order by the reduce kernel.  No atomics:
-// bitwise reproducible.
+// bitwise reproducible.  A workgroup's time grows with the in-degree of b
+// (Poisson-like for a random neighbour table), so the workgroups are
+// dispatched in decreasing in-degree (the order array): the long ones start
+// first instead of leaving a tail of idle compute units.  The order changes no
+// result.
 #include "sse_kernels.h"
 
 namespace sse {
@@ -112,7 +116,8 @@ __global__ __launch_bounds__(512) void bwd_mfma_kernel(Dims d, const double* __r
                                                        const double* __restrict__ Dg, const double* __restrict__ Ag,
                                                        const double* __restrict__ gS, cd calpha,
                                                        const int32_t* __restrict__ offset,
-                                                       const int32_t* __restrict__ edges, double* __restrict__ dG,
+                                                       const int32_t* __restrict__ edges,
+                                                       const int32_t* __restrict__ order, double* __restrict__ dG,
                                                        double* __restrict__ dApart) {
     using C = BwdCfg<NORB, NKZ, NW, EP>;
     constexpr int NN = C::NN, K2 = C::K2, TW = C::TW, MPAD = C::MPAD;
@@ -131,9 +136,10 @@ __global__ __launch_bounds__(512) void bwd_mfma_kernel(Dims d, const double* __r
     // energies fit 32 bits: the dispatcher admits ne < 2^28
     const int NE = (int)d.ne;
     const int nch = (NE + C::ECH - 1) / C::ECH;
-    const int64_t b = blockIdx.x / nch;
+    // atoms in decreasing in-degree: the longest workgroups are dispatched first
+    if (blockIdx.x / nch >= d.na) return;  // uniform for the workgroup, before any barrier
+    const int64_t b = order[blockIdx.x / nch];
     const int ch = (int)(blockIdx.x % nch);
-    if (b >= d.na) return;  // uniform for the workgroup, before any barrier
     const int E_lo = ch * C::ECH, E_hi = E_lo + C::ECH < NE ? E_lo + C::ECH : NE;
     const int32_t e_lo = offset[b], e_hi = offset[b + 1];
 
@@ -492,11 +498,11 @@ hipError_t bwd_mfma_prepare() {
 }
 
 hipError_t launch_bwd_mfma(const Dims& d, const double* G, const double* D, const double* A, const double* gS, cd calpha,
-                           const int32_t* offset, const int32_t* edges, double* dG, double* dApart,
-                           hipStream_t stream) {
+                           const int32_t* offset, const int32_t* edges, const int32_t* order, double* dG,
+                           double* dApart, hipStream_t stream) {
     const int64_t groups = d.na * bwd_mfma_shares(d);
     hipLaunchKernelGGL((bwd_mfma_kernel<10, 7, 10, kBwdEP>), dim3((unsigned)groups), dim3(BwdC::THREADS),
-                       BwdC::LDS_BYTES, stream, d, G, D, A, gS, calpha, offset, edges, dG, dApart);
+                       BwdC::LDS_BYTES, stream, d, G, D, A, gS, calpha, offset, edges, order, dG, dApart);
     return hipGetLastError();
 }
 

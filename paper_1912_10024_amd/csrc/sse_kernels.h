@@ -53,8 +53,8 @@ bool bwd_mfma_specialised(const Dims& d);
 int64_t bwd_mfma_shares(const Dims& d);
 hipError_t bwd_mfma_prepare();
 hipError_t launch_bwd_mfma(const Dims& d, const double* G, const double* D, const double* A, const double* gS, cd calpha,
-                           const int32_t* offset, const int32_t* edges, double* dG, double* dApart,
-                           hipStream_t stream);
+                           const int32_t* offset, const int32_t* edges, const int32_t* order, double* dG,
+                           double* dApart, hipStream_t stream);
 hipError_t launch_bwd(const Dims& d, const double* G, const double* Dp, const double* Dm, const double* A,
                       const int32_t* nbr, cd alpha, const double* gS, double* dG, double* dDp, double* dDm, double* dA,
                       void* ws, hipStream_t stream, bool signed_form, bool copy_g);
