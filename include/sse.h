@@ -217,7 +217,8 @@ int sse_forward_ex(const sse_dims* dims, const double* G, const double* Dp, cons
  *   ddH[a,n,j]        += alpha d g^H A_i B
  * Shifted G blocks are re-gathered, not stored.  The workspace
  * (sse_workspace_bytes(dims, 0, 1) bytes suffice for every call) holds the
- * reverse neighbour adjacency (4 * (3 na + 1 + na * nb) bytes, rounded up to
+ * reverse neighbour adjacency and the atoms' dispatch order (4 * (4 na + 1 +
+ * na * nb) bytes, rounded up to
  * 256) and, if ddH is wanted, S shares of every edge's dL/d(dH)
  * (16 * S * na * nb * 3 * norb^2 bytes, rounded up to 256), added in share
  * order, so results are bitwise reproducible: S = ceil(ne / 32) (one per range
@@ -258,11 +259,11 @@ int sse_backward_signed(const sse_dims* dims, const double* G, const double* Dp,
  * buffer.  Calls no hipMalloc, hipFree or allocating routine.  Dims whose
  * workspace for this call exceeds the array are rejected with
  * SSE_ERR_WORKSPACE before anything is launched: the reverse adjacency takes
- * 4 * (3 Na + 1 + Na * Nb) bytes (rounded up to 256), and with ddH the d(dH)
+ * 4 * (4 Na + 1 + Na * Nb) bytes (rounded up to 256), and with ddH the d(dH)
  * shares 16 * S * Na * Nb * 3 * Norb^2 more, S = ceil(NE / 32)
  * on the matrix-core shape (Norb = 10, Nkz = Nqz = 7, Nw = 10), S = Nkz otherwise
  * (at Nkz = 7, Norb = 10, Nb = 4, NE <= 224: about 500 atoms with ddH, about
- * 2.4 million without it).  dD reads dSigma in place (no atom-major copy:
+ * 2.1 million without it).  dD reads dSigma in place (no atom-major copy:
  * slower than sse_backward's, the same sums).  Every call on one GPU uses that GPU's
  * array (the current device's): calls that overlap on one GPU race.  The
  * kernels rewrite every part of the array they read, so no clearing is needed
