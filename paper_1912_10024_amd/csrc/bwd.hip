@@ -90,9 +90,9 @@ __global__ void rcsr_sort_kernel(int64_t na, const int32_t* __restrict__ offset,
     }
 }
 
-// atoms in decreasing in-degree (the matrix-core dG / d gradH kernel's dispatch
-// order: a workgroup's time grows with the in-degree of its atom, so the longest
-// start first and the shortest fill the end).  One workgroup; degrees above 255
+// atoms in decreasing in-degree (the dispatch order of both dG / d gradH kernels:
+// a workgroup's time grows with the in-degree of its atom, so the longest start
+// first and the shortest fill the end).  One workgroup; degrees above 255
 // share the first bucket; the order within a bucket is arbitrary, which changes
 // no result (every workgroup of that kernel owns its outputs).
 __global__ __launch_bounds__(1024) void rcsr_order_kernel(int64_t na, const int32_t* __restrict__ count,
@@ -219,6 +219,7 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_dg_dh_kernel(Dims d, const do
                                                                 const double* __restrict__ gS, cd calpha,
                                                                 const int32_t* __restrict__ offset,
                                                                 const int32_t* __restrict__ edges,
+                                                                const int32_t* __restrict__ order,
                                                                 double* __restrict__ dG, double* __restrict__ dApart) {
     extern __shared__ double smem[];
     const int N = (int)d.norb, NN = N * N;
@@ -236,13 +237,15 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_dg_dh_kernel(Dims d, const do
                                             // sT, sC, sE (9 N^2), which are written only after the merge
     const int tid = threadIdx.x;
     // One workgroup per (neighbour atom b, momentum k'): Nkz times as many
-    // equal workgroups as atoms, so the launch has no partly filled last round.
-    // The Nkz workgroups of one atom get ids on the same XCD (they read the
-    // same D, grad H and g blocks).
+    // workgroups as atoms.  The Nkz workgroups of one atom get ids on the same
+    // XCD (they read the same D, grad H and g blocks); the atoms come in
+    // decreasing in-degree (a workgroup walks the edges into its atom), so the
+    // longest workgroups start first.
     const int64_t bid = blockIdx.x, span = 8 * d.nkz;
-    const int64_t b = (bid / span) * 8 + bid % 8;
+    const int64_t pos = (bid / span) * 8 + bid % 8;
     const int64_t kp = (bid % span) / 8;
-    if (b >= d.na) return;  // uniform for the workgroup, before any barrier
+    if (pos >= d.na) return;  // uniform for the workgroup, before any barrier
+    const int64_t b = order[pos];
     const int32_t e_lo = offset[b], e_hi = offset[b + 1];
 
     // slots >= 1 of dG are not read by the forward map: zero
@@ -501,7 +504,7 @@ hipError_t launch_bwd(const Dims& d, const double* G, const double* Dp, const do
         const unsigned g2 = (unsigned)((d.na + 255) / 256 < 4096 ? (d.na + 255) / 256 : 4096);
         hipLaunchKernelGGL(rcsr_sort_kernel, dim3(g2), dim3(256), 0, stream, d.na, offset, edges);
         int32_t* order = edges + d.na * d.nb;
-        if (mfma) hipLaunchKernelGGL(rcsr_order_kernel, dim3(1), dim3(1024), 0, stream, d.na, count, order);
+        hipLaunchKernelGGL(rcsr_order_kernel, dim3(1), dim3(1024), 0, stream, d.na, count, order);
         double* dApart = dA ? reinterpret_cast<double*>(reinterpret_cast<char*>(ws) + bwd_csr_bytes(d)) : nullptr;
         hipError_t e;
         if (mfma) {
@@ -509,7 +512,7 @@ hipError_t launch_bwd(const Dims& d, const double* G, const double* Dp, const do
         } else {
             const int64_t groups = (d.na + 7) / 8 * 8 * d.nkz;
             hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(kBwdThreads), lds, stream, d, G, Dp, Dm, A, gS,
-                               calpha, offset, edges, dG, dApart);
+                               calpha, offset, edges, order, dG, dApart);
             e = hipGetLastError();
         }
         if (e != hipSuccess) return e;
