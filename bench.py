@@ -182,6 +182,18 @@ def recorded_traffic(record, sources):
     return float(kv["fetch_bytes"]) + float(kv["write_bytes"])
 
 
+def fwd_mfma_dispatches(d, dev) -> int:
+    """Kernel dispatches of one fp64 / fp32 forward call: the atoms go in batches
+    of about twelve rounds of workgroups (12 * compute units / Norb, a multiple of
+    8), as launch_fwd_flags in fwd_mfma.hip issues them."""
+    import torch
+
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    batch = max(8, 12 * cus // d.norb // 8 * 8)
+    na8 = (d.na + 7) // 8 * 8
+    return (na8 + batch - 1) // batch
+
+
 def time_form(sse, G, D, dH, nbr, S, ws, form, steps, warmup, dev):
     import torch
 
@@ -397,6 +409,10 @@ def main():
                                      if form in traffic_records and args.config == "device" else None),
                          "flops_per_launch": mfma_flops[form], "what": whats[form]},
         }
+        if form in ("fp64", "fp32"):
+            # this kernel runs as several dispatches per call; the roofline's launch
+            # is the call (flops, traffic and HIP-event time all per call)
+            res[form]["roofline"]["dispatches_per_call"] = fwd_mfma_dispatches(d, dev)
         if cpu is not None:
             res[form]["err"] = sampled_error(S, cpu_pts, cpu_ref)
         del S, ws

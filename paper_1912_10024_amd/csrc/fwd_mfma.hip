@@ -26,10 +26,13 @@
 // (a second small GEMM), and forms the X rows of the chunk after that on the
 // vector ALUs (double-buffered in LDS).  The two waves of a SIMD run these
 // phases in opposite orders, so the latency-bound phases of one wave meet
-// the matrix work of the other.  At the end of an energy block the waves add
+// the matrix work of the other.  The host launches the atoms in batches of
+// about twelve rounds of workgroups, so that the row workgroups of an atom
+// keep sharing its neighbours' G blocks in L2.  At the end of an energy block the waves add
 // their accumulators into a ring of output planes (LDS, fp64) in phases that
 // touch disjoint entries, so results are bitwise reproducible; planes that
 // can receive no more contributions are scaled by alpha and written out.
+#include <algorithm>
 #include <type_traits>
 
 #include "fwd_common.h"
@@ -178,7 +181,7 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
                                                        const double* __restrict__ Ag,
                                                        const double* __restrict__ Bg,
                                                        const int32_t* __restrict__ nbr, cd alpha,
-                                                       double* __restrict__ S) {
+                                                       double* __restrict__ S, int64_t a0) {
     using C = Fwd64<NORB, NKZ, NW, NB, EB, PREC, HBA>;
     using O = Oper<PREC>;
     using T = typename O::T;
@@ -199,10 +202,11 @@ __global__ __launch_bounds__(512) void fwd_mfma_kernel(Dims d, const double* __r
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     // XCD-aware mapping: the Norb workgroups of one atom share its D, grad H and
-    // neighbour G blocks, so they get block ids that land on the same XCD.
+    // neighbour G blocks, so they get block ids that land on the same XCD; this
+    // launch covers the atoms from a0 (a multiple of 8).
     const int64_t bid = blockIdx.x;
     const int r = (int)((bid >> 3) % NORB);
-    const int64_t a = ((bid >> 3) / NORB) * 8 + (bid & 7);
+    const int64_t a = a0 + ((bid >> 3) / NORB) * 8 + (bid & 7);
     if (a >= d.na) return;  // uniform for the whole workgroup, before any barrier
 
     // ---- stage the atom's D table, grad H; clear buffers
@@ -606,9 +610,24 @@ static hipError_t launch_fwd_flags(const Dims& d, const double* G, const double*
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)C::LDS_BYTES);
     if (e != hipSuccess) return e;
-    const int64_t groups = ((d.na + 7) / 8) * 8 * NORB;
-    hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(C::THREADS), C::LDS_BYTES, stream, d, G, D, A, B, nbr, alpha,
-                       S);
+    // The Norb row workgroups of an atom start together and share its G blocks in
+    // L2 while they stay within a few chunks of each other; over a long launch
+    // they drift apart (each compute unit runs its workgroups one after another
+    // and their durations vary) and the sharing is lost.  Launches of about
+    // twelve rounds of workgroups (304 atoms on 256 compute units at Norb = 10)
+    // start every atom's rows together again; the boundaries cost no measurable
+    // time at the device workload.
+    int dev = 0, cus = 0;
+    e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const int64_t na8 = ((d.na + 7) / 8) * 8;
+    const int64_t batch = std::max<int64_t>(8, (int64_t)12 * cus / NORB / 8 * 8);
+    for (int64_t a0 = 0; a0 < na8; a0 += batch) {
+        const int64_t atoms = std::min(batch, na8 - a0);
+        hipLaunchKernelGGL(kern, dim3((unsigned)(atoms * NORB)), dim3(C::THREADS), C::LDS_BYTES, stream, d, G, D, A, B,
+                           nbr, alpha, S, a0);
+    }
     return hipGetLastError();
 }
 
