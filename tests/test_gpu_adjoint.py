@@ -238,3 +238,39 @@ def test_central_differences_mid(mid, name):
             gmax = max(gmax, abs(an))
     print(f"  FD {name}: max |fd - grad| = {worst:.3e}, max |grad| = {gmax:.3e}, ratio {worst / gmax:.3e}", flush=True)
     assert worst <= 1e-7 * gmax
+
+
+def test_backward_hub_atom_dot_products():
+    """A neighbour table with a hub: every atom but 0 has atom 0 in slot 0, so atom
+    0 has in-degree 299, past the 255 of the dispatch order's last degree bucket,
+    and its workgroups walk 299 edges.  All three gradients satisfy their
+    dot-product identities exactly (up to rounding): L is linear in G and in D,
+    and quadratic in grad H, whose central difference with any step is then exact."""
+    d = Dims(nkz=7, ne=24, nqz=7, nw=10, na=300, nb=4, norb=10, g_slots=1)
+    rng = np.random.default_rng(31)
+
+    def cn(shape, s=1.0):
+        return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) * s
+
+    nbr = np.empty((d.na, d.nb), dtype=np.int32)
+    for a in range(d.na):
+        hub = 1 if a == 0 else 0
+        rest = rng.choice([b for b in range(d.na) if b not in (a, hub)], size=d.nb - 1, replace=False)
+        nbr[a] = [hub, *rest]
+    assert np.bincount(nbr.ravel(), minlength=d.na)[0] == d.na - 1
+    t = {"G": torch.from_numpy(anti_hermitian_blocks(cn(d.g_shape))).cuda(), "D": torch.from_numpy(cn(d.d_shape)).cuda(),
+         "dH": torch.from_numpy(cn(d.dh_shape, 0.1)).cuda(), "nbr": torch.from_numpy(nbr).cuda(),
+         "W": torch.from_numpy(cn(d.sigma_shape)).cuda()}
+    gS = t["W"].transpose(-1, -2).conj().contiguous()
+    dG, dD, ddH = sse.backward(t["G"], t["D"], t["dH"], t["nbr"], gS)
+    for name, grad in (("G", dG), ("D", dD)):
+        pert = torch.from_numpy(cn(tuple(grad.shape))).cuda()
+        lhs = float(torch.sum(grad.conj() * pert).real)
+        rhs = float(_L(t, **{name: pert}))
+        print(f"  hub dot-product {name}: {lhs:.12e} vs {rhs:.12e}", flush=True)
+        assert abs(lhs - rhs) <= 1e-11 * abs(rhs)
+    pert = torch.from_numpy(cn(d.dh_shape, 0.1)).cuda()
+    lhs = float(torch.sum(ddH.conj() * pert).real)
+    rhs = float((_L(t, dH=t["dH"] + pert) - _L(t, dH=t["dH"] - pert)) / 2)
+    print(f"  hub dot-product dH: {lhs:.12e} vs {rhs:.12e}", flush=True)
+    assert abs(lhs - rhs) <= 1e-10 * abs(rhs)
