@@ -156,7 +156,11 @@ int sse_effective_flops(const sse_dims* dims, double* f_eff);
 /*
  * Sigma = the operation above (Eq. 3).  precision is an sse_precision value;
  * every form reads the same fp64 inputs, gathers them in fp64 and reduces
- * over (qz, w, +/-) in fp64.  Sigma is fully overwritten.
+ * over (qz, w, +/-) in fp64.  Sigma is fully overwritten.  The matrix-core
+ * shapes (norb, nkz = nqz, nw, nb) are (10, 7, 10, 4), (10, 7, 10, 3) and
+ * (4, 3, 2, 4) for every precision, and (12, 7, 10, 4) for SSE_FP64 and
+ * SSE_FP32; other shapes take SSE_FP64 only, on a direct vector-ALU kernel
+ * (any other precision: SSE_ERR_PRECISION).
  */
 int sse_forward(const sse_dims* dims, const double* G, const double* D, const double* dH,
                 const int32_t* nbr, double alpha_re, double alpha_im, int precision,
@@ -197,8 +201,9 @@ int sse_forward_signed(const sse_dims* dims, const double* G, const double* Dp, 
  * dHba [na][nb][3][norb][norb] complex holds grad_j H_ba for the pair (a, b =
  * nbr[a,n]) (the layout of dH); NULL means the Hermitian reading dHba[a,n,j] =
  * dH[a,n,j]^H, which makes this call sse_forward_signed.  Every precision runs
- * on the matrix-core shapes (the fp64 kernel then works on energy blocks of
- * four, whose LDS holds the second table); other shapes take fp64 only.  Other
+ * on the matrix-core shapes with norb 10 or 4 (the fp64 kernel then works on
+ * energy blocks of four, whose LDS holds the second table); at norb 12 and on
+ * other shapes a stored dHba takes fp64 only, on the direct kernel.  Other
  * arguments, layouts, workspace and errors as for sse_forward_signed.
  */
 int sse_forward_ex(const sse_dims* dims, const double* G, const double* Dp, const double* Dm, const double* dH,

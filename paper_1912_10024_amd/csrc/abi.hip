@@ -154,7 +154,7 @@ int forward_impl(const sse_dims* dims, const double* G, const double* Dp, const 
     const sse::cd alpha{alpha_re, alpha_im};
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e;
-    if (sse::fwd_mfma_specialised(d)) {
+    if (sse::fwd_mfma_supports(d, precision, dHba != nullptr)) {
         if (Dm == Dp) {
             e = sse::launch_fwd_mfma(d, precision, G, Dp, dH, dHba, nbr, alpha, Sigma, s);
         } else {

@@ -649,7 +649,16 @@ static hipError_t launch_fwd(const Dims& d, const double* G, const double* D, co
 bool fwd_mfma_specialised(const Dims& d) {
     if (d.ne >= (int64_t(1) << 28)) return false;  // 32-bit chunk indices
     return (d.norb == 10 && d.nkz == 7 && d.nw == 10 && d.nb == 4) || (d.norb == 4 && d.nkz == 3 && d.nw == 2 && d.nb == 4) ||
-           (d.norb == 10 && d.nkz == 7 && d.nw == 10 && d.nb == 3);
+           (d.norb == 10 && d.nkz == 7 && d.nw == 10 && d.nb == 3) || (d.norb == 12 && d.nkz == 7 && d.nw == 10 && d.nb == 4);
+}
+
+// Norb = 12 (the paper's orbital count) fits the LDS with blocks of 4 source
+// energies, for fp64 and fp32 operands and grad H^H as the right factor only
+// (a stored grad H_ba table, or the 16-bit layout, would not fit)
+bool fwd_mfma_supports(const Dims& d, int precision, bool hba) {
+    if (!fwd_mfma_specialised(d)) return false;
+    if (d.norb == 12) return (precision == SSE_FP64 || precision == SSE_FP32) && !hba;
+    return true;
 }
 
 // energy blocks of 8 source energies; with a stored grad H_ba the fp64 form
@@ -671,6 +680,8 @@ static hipError_t dispatch_fwd(const Dims& d, const double* G, const double* D, 
         return launch_shape<10, 7, 10, 3, PREC>(d, G, D, A, B, nbr, alpha, S, stream, flags);
     if (d.norb == 4 && d.nkz == 3 && d.nw == 2 && d.nb == 4)
         return launch_shape<4, 3, 2, 4, PREC>(d, G, D, A, B, nbr, alpha, S, stream, flags);
+    if (d.norb == 12 && d.nkz == 7 && d.nw == 10 && d.nb == 4 && !B)
+        return launch_fwd<12, 7, 10, 4, 4, PREC, false>(d, G, D, A, B, nbr, alpha, S, stream, flags);
     return hipErrorInvalidValue;
 }
 

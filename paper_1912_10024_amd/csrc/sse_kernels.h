@@ -25,6 +25,8 @@ hipError_t launch_fwd_generic(const Dims& d, const double* G, const double* Dp, 
 // kBranchPlus) and whether the result is added to Sigma (kAccumulate)
 // B: stored grad_j H_ba blocks (layout of A) as the right factor, or nullptr for A^H
 bool fwd_mfma_specialised(const Dims& d);
+// whether the matrix-core forward takes this precision (and a stored grad H_ba) at these dims
+bool fwd_mfma_supports(const Dims& d, int precision, bool hba);
 hipError_t launch_fwd_mfma(const Dims& d, int precision, const double* G, const double* D, const double* A,
                            const double* B, const int32_t* nbr, cd alpha, double* S, hipStream_t stream,
                            int flags = kBranchMinus | kBranchPlus);
