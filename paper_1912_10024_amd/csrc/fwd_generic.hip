@@ -1,7 +1,9 @@
 // Direct (term-by-term) forward kernel for shapes without a matrix-core
 // specialisation.  One workgroup per output block Sigma[k,E,a]; every term of
-// Eq. 3 is formed as (grad_i H . G_b) . grad_j H_ba in fp64 on the vector ALUs,
-// with grad_j H_ba the stored block B[a,n,j] when given, else grad_j H^H.
+// Eq. 3 is formed in fp64 on the vector ALUs as sum_i X_i . Y_i with
+// X_i = grad_i H . G_b and Y_i = sum_j D_ij grad_j H_ba (the coefficients summed
+// into the right factor first: 6 block products per term instead of 12), with
+// grad_j H_ba the stored block B[a,n,j] when given, else grad_j H^H.
 #include "sse_kernels.h"
 
 namespace sse {
@@ -21,7 +23,8 @@ __global__ __launch_bounds__(kGenThreads) void fwd_generic_kernel(Dims d, const 
     extern __shared__ double smem[];
     const int N = (int)d.norb, NN = N * N;
     cd* sG = reinterpret_cast<cd*>(smem);  // [N][N]
-    cd* sT = sG + NN;                      // [3][N][N]
+    cd* sT = sG + NN;                      // [3][N][N]  X_i
+    cd* sY = sT + 3 * NN;                  // [3][N][N]  Y_i
     const int tid = threadIdx.x;
     const int64_t nblk = d.nkz * d.ne * d.na;
     for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
@@ -41,33 +44,36 @@ __global__ __launch_bounds__(kGenThreads) void fwd_generic_kernel(Dims d, const 
                         const double* Gb = G + 2 * off_G(d, kp, ep, b);
                         for (int x = tid; x < NN; x += kGenThreads) sG[x] = cload(Gb, x);
                         __syncthreads();
+                        // G at E - w: coefficient at +w; G at E + w: coefficient at -w
+                        const double* Dq = (s > 0 ? Dp : Dm) + 2 * off_D(d, q, w - 1, a, n);
                         for (int x = tid; x < 3 * NN; x += kGenThreads) {
                             const int i = x / NN, r = (x % NN) / N, u = x % N;
                             const double* Ai = A + 2 * off_A(d, a, n, i);
                             cd t = cd{0.0, 0.0};
                             for (int tt = 0; tt < N; ++tt) cfma(t, cload(Ai, r * N + tt), sG[tt * N + u]);
                             sT[x] = t;
+                            // Y_i[r][u] = sum_j D_ij R_j[r][u], R_j = B_j or grad_j H^H
+                            cd y = cd{0.0, 0.0};
+                            for (int j = 0; j < 3; ++j) {
+                                cd rj;
+                                if (B) {
+                                    rj = cload(B + 2 * off_A(d, a, n, j), r * N + u);
+                                } else {
+                                    const cd aj = cload(A + 2 * off_A(d, a, n, j), u * N + r);
+                                    rj = cd{aj.re, -aj.im};
+                                }
+                                cfma(y, cload(Dq, i * 3 + j), rj);
+                            }
+                            sY[x] = y;
                         }
                         __syncthreads();
-                        // G at E - w: coefficient at +w; G at E + w: coefficient at -w
-                        const double* Dq = (s > 0 ? Dp : Dm) + 2 * off_D(d, q, w - 1, a, n);
 #pragma unroll
                         for (int xi = 0; xi < kGenMaxPerThread; ++xi) {
                             const int x = tid + xi * kGenThreads;
                             if (x >= NN) break;
                             const int r = x / N, c = x % N;
                             for (int i = 0; i < 3; ++i)
-                                for (int j = 0; j < 3; ++j) {
-                                    cd u = cd{0.0, 0.0};
-                                    if (B) {
-                                        const double* Bj = B + 2 * off_A(d, a, n, j);
-                                        for (int uu = 0; uu < N; ++uu) cfma(u, sT[i * NN + r * N + uu], cload(Bj, uu * N + c));
-                                    } else {
-                                        const double* Aj = A + 2 * off_A(d, a, n, j);
-                                        for (int uu = 0; uu < N; ++uu) cfma_conj(u, sT[i * NN + r * N + uu], cload(Aj, c * N + uu));
-                                    }
-                                    cfma(acc[xi], cload(Dq, i * 3 + j), u);
-                                }
+                                for (int uu = 0; uu < N; ++uu) cfma(acc[xi], sT[i * NN + r * N + uu], sY[i * NN + uu * N + c]);
                         }
                         __syncthreads();
                     }
@@ -87,7 +93,10 @@ hipError_t launch_fwd_generic(const Dims& d, const double* G, const double* Dp, 
                               const double* B, const int32_t* nbr, cd alpha, double* S, hipStream_t stream) {
     const int64_t nblk = d.nkz * d.ne * d.na;
     const unsigned grid = (unsigned)(nblk < (int64_t)(1 << 30) ? nblk : (1 << 30));
-    const size_t lds = sizeof(cd) * 4 * (size_t)(d.norb * d.norb);
+    const size_t lds = sizeof(cd) * 7 * (size_t)(d.norb * d.norb);  // G, X_i, Y_i
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fwd_generic_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fwd_generic_kernel, dim3(grid), dim3(kGenThreads), lds, stream, d, G, Dp, Dm, A, B, nbr, alpha, S);
     return hipGetLastError();
 }
