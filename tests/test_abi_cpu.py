@@ -170,3 +170,32 @@ def test_signed_forward_reduced_precision_needs_matrix_core_shape(lib):
         rc = lib.sse_forward_signed(ctypes.byref(generic), *[P(1)] * 5, 0.0, 1.0, prec, P(1), P(1), 256, None)
         assert rc == _lib.SSE_ERR_PRECISION
         assert b"precision" in lib.sse_last_error()
+
+
+def _round256(x):
+    return (x + 255) // 256 * 256
+
+
+@pytest.mark.parametrize("dims", [
+    Dims(nkz=7, ne=256, nqz=7, nw=10, na=1024, nb=4, norb=10, g_slots=1),   # matrix-core adjoint shape
+    Dims(nkz=7, ne=70, nqz=7, nw=10, na=37, nb=3, norb=10, g_slots=2),
+    Dims(nkz=3, ne=16, nqz=3, nw=2, na=16, nb=4, norb=4, g_slots=5),        # other kernels
+])
+def test_backward_workspace_matches_the_documented_layout(lib, dims):
+    """sse_workspace_bytes(op = 1) is what include/sse.h documents for the
+    adjoint: the reverse adjacency and dispatch order, 4 (4 na + 1 + na nb)
+    bytes; the d grad H shares, 16 S na nb 3 norb^2 (S = ceil(ne / 32) on the
+    matrix-core shape, nkz otherwise, and nkz for the signed form); the
+    atom-major copy of dSigma on the matrix-core phonon shape, 16 na nkz ne
+    norb^2 (one-table form); each rounded up to 256, the larger of the two forms."""
+    d = dims
+    mfma = d.norb == 10 and d.nkz == 7 and d.nqz == 7 and d.nw == 10
+    csr = _round256(4 * (4 * d.na + 1 + d.na * d.nb))
+    shares = (d.ne + 31) // 32 if mfma else d.nkz
+    one_table = csr + _round256(16 * shares * d.na * d.nb * 3 * d.norb ** 2)
+    if mfma and d.nb in (3, 4):
+        one_table += _round256(16 * d.na * d.nkz * d.ne * d.norb ** 2)
+    signed = csr + _round256(16 * d.nkz * d.na * d.nb * 3 * d.norb ** 2)
+    need = ctypes.c_size_t(0)
+    assert lib.sse_workspace_bytes(ctypes.byref(_lib.SSEDims.of(d)), 0, 1, ctypes.byref(need)) == _lib.SSE_OK
+    assert need.value == max(one_table, signed)
