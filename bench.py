@@ -38,7 +38,9 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--config", default="device", choices=["tiny", "mid", "device"])
+    p.add_argument("--config", default="device", choices=["tiny", "mid", "device", "mid12"],
+                   help="workload; mid12: the mid workload with 12 orbitals (the paper's count), fp64 and fp32 "
+                        "forms only, with --no-phonon --no-adjoint")
     p.add_argument("--forms", default="fp64,fp32,bf16x2,fp16x2,fp16",
                    help="comma-separated operand precisions to time; the first is the headline value "
                         "(fp16 and fp16_unscaled: the single-term comparison forms)")
@@ -339,6 +341,17 @@ def main():
     from paper_1912_10024_amd import flops, sse
     from paper_1912_10024_amd.inputs import CONFIGS, CONFIG_INDEX, generate_device
 
+    if args.config == "mid12":
+        # the Norb = 12 instance of the matrix-core forward: the mid sizes with 12
+        # orbitals (inputs drawn from the mid workload's streams)
+        from paper_1912_10024_amd.inputs import Dims
+
+        CONFIGS = dict(CONFIGS, mid12=Dims(nkz=7, ne=256, nqz=7, nw=10, na=1024, nb=4, norb=12, g_slots=1))
+        CONFIG_INDEX = dict(CONFIG_INDEX, mid12=CONFIG_INDEX["mid"])
+        bad = [f for f in args.forms.split(",") if f.strip() not in ("fp64", "fp32")]
+        if bad or not (args.no_phonon and args.no_adjoint):
+            sys.exit("--config mid12 takes --forms fp64,fp32 (no 16-bit instance at 12 orbitals) with "
+                     "--no-phonon --no-adjoint")
     d = CONFIGS[args.config]
     dev = torch.device("cuda:0")
     if args.only_adjoint:
