@@ -44,6 +44,9 @@ SHAPES = [
     (Dims(nkz=7, ne=12, nqz=7, nw=10, na=5, nb=4, norb=10, g_slots=1), 2),      # nw close to ne
     (Dims(nkz=3, ne=21, nqz=3, nw=4, na=7, nb=3, norb=5, g_slots=2), 3),        # generic shape
     (Dims(nkz=1, ne=9, nqz=1, nw=3, na=4, nb=2, norb=2, g_slots=1), 4),
+    (Dims(nkz=3, ne=11, nqz=3, nw=3, na=7, nb=5, norb=10, g_slots=1), 5),       # direct kernel, 2 threads per element
+    (Dims(nkz=2, ne=7, nqz=2, nw=2, na=4, nb=2, norb=18, g_slots=1), 6),        # direct kernel, factors not staged
+    (Dims(nkz=1, ne=3, nqz=1, nw=1, na=3, nb=2, norb=32, g_slots=1), 7),        # direct kernel, largest Norb
 ]
 
 
