@@ -38,9 +38,11 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--config", default="device", choices=["tiny", "mid", "device", "mid12"],
+    p.add_argument("--config", default="device", choices=["tiny", "mid", "device", "mid12", "direct5"],
                    help="workload; mid12: the mid workload with 12 orbitals (the paper's count), fp64 and fp32 "
-                        "forms only, with --no-phonon --no-adjoint")
+                        "forms only, with --no-phonon --no-adjoint; direct5: 1024 atoms, NE 64 with 5 "
+                        "neighbours (no matrix-core instance: the direct fp64 kernel), fp64 only, with "
+                        "--no-phonon --no-adjoint")
     p.add_argument("--forms", default="fp64,fp32,bf16x2,fp16x2,fp16",
                    help="comma-separated operand precisions to time; the first is the headline value "
                         "(fp16 and fp16_unscaled: the single-term comparison forms)")
@@ -352,6 +354,17 @@ def main():
         if bad or not (args.no_phonon and args.no_adjoint):
             sys.exit("--config mid12 takes --forms fp64,fp32 (no 16-bit instance at 12 orbitals) with "
                      "--no-phonon --no-adjoint")
+    if args.config == "direct5":
+        # a shape without a matrix-core instance (one neighbour more than the
+        # instances): the direct fp64 kernel on the vector ALUs
+        from paper_1912_10024_amd.inputs import Dims
+
+        CONFIGS = dict(CONFIGS, direct5=Dims(nkz=7, ne=64, nqz=7, nw=10, na=1024, nb=5, norb=10, g_slots=1))
+        CONFIG_INDEX = dict(CONFIG_INDEX, direct5=CONFIG_INDEX["mid"])
+        if args.forms.strip() != "fp64" or not (args.no_phonon and args.no_adjoint):
+            sys.exit("--config direct5 takes --forms fp64 (the direct kernel is fp64 only) with "
+                     "--no-phonon --no-adjoint")
+    direct = args.config == "direct5"
     d = CONFIGS[args.config]
     dev = torch.device("cuda:0")
     if args.only_adjoint:
@@ -422,7 +435,13 @@ def main():
                                      if form in traffic_records and args.config == "device" else None),
                          "flops_per_launch": mfma_flops[form], "what": whats[form]},
         }
-        if form in ("fp64", "fp32"):
+        if direct:
+            # one dispatch of the direct kernel; its fp64 arithmetic runs on the
+            # vector ALUs, whose fp64 peak equals the matrix cores' one
+            res[form]["roofline"].update(bound="alu", dispatches_per_call=1,
+                                         what="useful fp64 flops of the regrouped count (flops.pd_useful_flops), "
+                                              "executed by the direct kernel on the vector ALUs")
+        elif form in ("fp64", "fp32"):
             # this kernel runs as several dispatches per call; the roofline's launch
             # is the call (flops, traffic and HIP-event time all per call)
             res[form]["roofline"]["dispatches_per_call"] = fwd_mfma_dispatches(d, dev)
